@@ -1,0 +1,33 @@
+"""Vecchia oracle: plain FP64 CPU reference implementation.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call this package.  The GPU
+library never links or calls it, and it shares no code with the GPU library.
+
+Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``):
+  raw_sums      pinned: dense exact GP at full conditioning (Section 2.1, A5),
+                joint-minus-marginal dense forms at any m, AR(1) closed form
+                for the 1-D exponential, m = 0 closed form, sigma2 identities,
+                finite differences of the log-likelihood.
+  cov_matrix    pinned: Matern via the Bessel-K definition (scipy), and
+                finite differences for the parameter derivatives.
+  combine       pinned through the dense exact GP and the AR(1) closed form.
+  fisher_step   pinned: the Eq. (4) update is a fixed point at the MLE of the
+                AR(1) closed form (scipy optimiser).
+"""
+
+from .oracle import (  # noqa: F401
+    FAMILY_ISO,
+    FAMILY_SPACETIME,
+    OracleError,
+    build,
+    combine,
+    cov_matrix,
+    fisher_step,
+    fit,
+    loglik_grad_info,
+    nparms,
+    nraw,
+    raw_sums,
+    unpack_raw,
+)

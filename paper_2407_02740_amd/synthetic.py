@@ -1,0 +1,267 @@
+"""Seeded synthetic workloads shaped like the paper's data (Section 4.2).
+
+This module is the one input source shared by the GPU library's callers and by
+the test oracle.  It contains no Vecchia arithmetic: it only draws locations,
+orders them, finds each observation's nearest previously ordered neighbours,
+and draws a response.  The paper's datasets (Jason-3, MODIS/Terra, UCI
+Elevators) are not available; these generators stand in for them with the same
+shapes, sizes and structure.
+
+Workloads (names follow the covariance model of Section 4.3, Eq. 5-6):
+
+* ``small_exponential``  n = 2000 uniform on [0,1]^2, exact maxmin ordering,
+  m = 10, exponential (sigma2, rho, tau2) = (1, 0.1, 0.01), intercept only;
+  y is an exact draw of the Gaussian process (dense Cholesky of the full
+  covariance, the model of Eq. 5).
+* ``matern_plane``  n = 262,144 distinct points uniform on [0,1]^2 (5% exact
+  duplicates drawn then removed), approximate maxmin ordering, m = 30,
+  Matern nu = 3/2 (2.0, 0.05, 0.05), X = [1, x1, x2], beta = (1, -0.5, 0.3).
+* ``satellite_spacetime``  64 time slices x 64 passes x 256 points along
+  sinusoidal ground tracks (|lat| <= 60 deg, along-track banding), locations
+  embedded in R^3 on the unit sphere plus time (Section 4.3: satellite data in
+  R^3), space-time exponential (1.0, rho_s = chord of 5 deg, rho_t = 3 slices,
+  0.1), m = 30, intercept only.
+
+For the two large workloads the response is a random-Fourier-feature draw of
+the same stationary covariance plus the nugget noise (not a Vecchia draw), so
+that this module stays free of the method's arithmetic.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+FAMILY_ISO = 0
+FAMILY_SPACETIME = 1
+
+
+# ----------------------------------------------------------------------------
+# ordering
+# ----------------------------------------------------------------------------
+def maxmin_exact(locs: np.ndarray) -> np.ndarray:
+    """Exact maxmin ordering: start at the point nearest the centroid, then
+    repeatedly take the point farthest from all points taken so far."""
+    n = len(locs)
+    order = np.empty(n, dtype=np.int64)
+    first = int(np.argmin(((locs - locs.mean(0)) ** 2).sum(1)))
+    mind = ((locs - locs[first]) ** 2).sum(1)
+    mind[first] = -1.0
+    order[0] = first
+    for k in range(1, n):
+        j = int(np.argmax(mind))
+        order[k] = j
+        dj = ((locs - locs[j]) ** 2).sum(1)
+        np.minimum(mind, dj, out=mind)
+        mind[j] = -1.0
+        # points already taken keep -1 (dj >= 0 never lowers them below -1)
+    return order
+
+
+def maxmin_approx(locs: np.ndarray, seed: int = 0) -> np.ndarray:
+    """Approximate maxmin ordering by bit-reversed Morton codes.
+
+    Coordinates are quantised to a 2^B grid per dimension (B chosen so a cell
+    holds about one point); the interleaved cell code is bit-reversed so that
+    coarse lattices come first and finer ones fill in between (coarse to
+    fine); ties are broken at random.
+    """
+    n, d = locs.shape
+    rng = np.random.default_rng(seed)
+    lo = locs.min(0)
+    span = np.maximum(locs.max(0) - lo, 1e-300)
+    B = max(1, int(math.ceil(math.log2(max(n, 2)) / d)))
+    B = min(B, 60 // d)
+    q = np.minimum(((locs - lo) / span * (1 << B)).astype(np.int64), (1 << B) - 1)
+    code = np.zeros(n, dtype=np.int64)
+    bit = 0
+    # interleave from the most significant grid bit down
+    for b in range(B - 1, -1, -1):
+        for k in range(d):
+            code |= ((q[:, k] >> b) & 1) << (B * d - 1 - bit)
+            bit += 1
+    # bit-reverse the B*d-bit code
+    rev = np.zeros(n, dtype=np.int64)
+    for b in range(B * d):
+        rev |= ((code >> b) & 1) << (B * d - 1 - b)
+    tie = rng.random(n)
+    return np.lexsort((tie, rev))
+
+
+# ----------------------------------------------------------------------------
+# nearest previously ordered neighbours
+# ----------------------------------------------------------------------------
+def find_ordered_nn(locs: np.ndarray, m: int, workers: int = -1) -> np.ndarray:
+    """NNarray[n][m+1] (int32, 0-based): row i = [i, its min(i, m) nearest
+    neighbours among observations 0..i-1 by increasing distance, -1 ...]."""
+    from scipy.spatial import cKDTree
+
+    n = len(locs)
+    NN = np.full((n, m + 1), -1, dtype=np.int32)
+    NN[:, 0] = np.arange(n, dtype=np.int32)
+    if m == 0:
+        return NN
+    # brute force for the first few points
+    head = min(n, max(4 * (m + 1), 64))
+    for i in range(1, head):
+        q = min(i, m)
+        dist = ((locs[:i] - locs[i]) ** 2).sum(1)
+        idx = np.argsort(dist, kind="stable")[:q]
+        NN[i, 1:q + 1] = idx
+    # doubling blocks: a tree on points [0, b1) serves queries for [b0, b1)
+    b0 = head
+    while b0 < n:
+        b1 = min(n, 2 * b0)
+        tree = cKDTree(locs[:b1])
+        rows = np.arange(b0, b1)
+        k = min(b1, 3 * (m + 1))
+        todo = rows
+        while len(todo):
+            dist, idx = tree.query(locs[todo], k=k, workers=workers)
+            if k == 1:
+                idx = idx[:, None]
+            valid = idx < todo[:, None]
+            cnt = valid.sum(1)
+            ok = cnt >= m
+            if ok.any():
+                sel_rows = todo[ok]
+                v = valid[ok]
+                ii = idx[ok]
+                # first m valid entries in distance order
+                pos = np.cumsum(v, axis=1)
+                keep = v & (pos <= m)
+                NN[sel_rows, 1:] = ii[keep].reshape(-1, m)
+            todo = todo[~ok]
+            if k >= b1:
+                break
+            k = min(b1, 2 * k)
+        b0 = b1
+    return NN
+
+
+# ----------------------------------------------------------------------------
+# responses
+# ----------------------------------------------------------------------------
+def rff_field(scaled_locs: np.ndarray, nu: float, n_features: int, rng,
+              chunk: int = 1 << 16) -> np.ndarray:
+    """Unit-variance draw of a stationary Matern field in already range-scaled
+    coordinates by random Fourier features.  For correlation f_nu(|x|) with
+    h = |x| (no sqrt(2 nu) factor) the spectral density is proportional to
+    (1 + |w|^2)^-(nu + D/2), i.e. w = Z / sqrt(V), Z ~ N(0, I_D), V ~ chi2(2 nu)."""
+    n, D = scaled_locs.shape
+    Z = rng.standard_normal((n_features, D))
+    V = rng.chisquare(2.0 * nu, size=n_features)
+    W = Z / np.sqrt(V)[:, None]
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
+    out = np.empty(n)
+    scale = math.sqrt(2.0 / n_features)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        out[a:b] = scale * np.cos(scaled_locs[a:b] @ W.T + phase).sum(1)
+    return out
+
+
+def _exact_gp_draw(locs, covparms, rng):
+    """Exact draw of the model of Eq. 5 (exponential covariance plus nugget)."""
+    sigma2, rho, tau2 = covparms
+    diff = locs[:, None, :] - locs[None, :, :]
+    dist = np.sqrt((diff ** 2).sum(-1))
+    S = sigma2 * np.exp(-dist / rho) + sigma2 * tau2 * np.eye(len(locs))
+    C = np.linalg.cholesky(S)
+    return C @ rng.standard_normal(len(locs))
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+def _pack(name, locs, NN, y, X, covparms, family, nu, nspace, m):
+    return dict(name=name, locs=np.ascontiguousarray(locs, dtype=np.float64),
+                NN=np.ascontiguousarray(NN, dtype=np.int32),
+                y=np.ascontiguousarray(y, dtype=np.float64),
+                X=np.ascontiguousarray(X, dtype=np.float64),
+                covparms=np.asarray(covparms, dtype=np.float64), family=family, nu=float(nu),
+                nspace=int(nspace), m=int(m), n=len(y), p=X.shape[1], d=locs.shape[1])
+
+
+def small_exponential(seed: int = 1, n: int = 2000, m: int = 10) -> dict:
+    rng = np.random.default_rng(seed)
+    locs = rng.random((n, 2))
+    locs = locs[maxmin_exact(locs)]
+    NN = find_ordered_nn(locs, m)
+    covparms = (1.0, 0.1, 0.01)
+    y = _exact_gp_draw(locs, covparms, rng)
+    X = np.ones((n, 1))
+    return _pack("small_exponential", locs, NN, y, X, covparms, FAMILY_ISO, 0.5, 0, m)
+
+
+def matern_plane(seed: int = 2, n: int = 262_144, m: int = 30, n_features: int = 512) -> dict:
+    rng = np.random.default_rng(seed)
+    base = rng.random((n, 2))
+    dup = base[rng.integers(0, n, size=int(0.05 * n))]
+    pts = np.concatenate([base, dup])
+    _, first = np.unique(pts, axis=0, return_index=True)
+    pts = pts[np.sort(first)]
+    while len(pts) < n:
+        extra = rng.random((n - len(pts), 2))
+        pts = np.concatenate([pts, extra])
+        _, first = np.unique(pts, axis=0, return_index=True)
+        pts = pts[np.sort(first)]
+    locs = pts[:n]
+    order = maxmin_exact(locs) if n <= 20_000 else maxmin_approx(locs, seed)
+    locs = locs[order]
+    NN = find_ordered_nn(locs, m)
+    covparms = (2.0, 0.05, 0.05)
+    nu = 1.5
+    X = np.column_stack([np.ones(n), locs[:, 0], locs[:, 1]])
+    beta = np.array([1.0, -0.5, 0.3])
+    f = rff_field(locs / covparms[1], nu, n_features, rng)
+    y = X @ beta + math.sqrt(covparms[0]) * f + math.sqrt(covparms[0] * covparms[2]) * \
+        rng.standard_normal(n)
+    return _pack("matern_plane", locs, NN, y, X, covparms, FAMILY_ISO, nu, 0, m)
+
+
+RHO_SPACE_5DEG = 2.0 * math.sin(math.radians(2.5))  # chord length of a 5 degree arc
+
+
+def satellite_tracks(slices: int, passes: int, per_pass: int, rng):
+    """lon/lat/time of points along sinusoidal ground tracks.
+
+    Each pass covers half an orbit: lat = 60 deg * sin(phi), lon = lon0 + phi
+    (degrees, wrapped to [-180, 180)), phi uniform on [0, pi), alternately
+    ascending and descending; t = slice index + a uniform offset that
+    increases along the pass."""
+    lon = np.empty((slices, passes, per_pass))
+    lat = np.empty_like(lon)
+    t = np.empty_like(lon)
+    for s in range(slices):
+        for k in range(passes):
+            phi = np.sort(rng.uniform(0.0, np.pi, per_pass))
+            if k % 2:
+                phi = phi[::-1]
+            lon0 = rng.uniform(-180.0, 180.0)
+            lat[s, k] = 60.0 * np.sin(phi) * (1 if k % 2 == 0 else -1)
+            lon[s, k] = (lon0 + np.degrees(phi) + 180.0) % 360.0 - 180.0
+            t[s, k] = s + np.sort(rng.uniform(0.0, 1.0, per_pass))
+    return lon.ravel(), lat.ravel(), t.ravel()
+
+
+def satellite_spacetime(seed: int = 3, slices: int = 64, passes: int = 64, per_pass: int = 256,
+                        m: int = 30, n_features: int = 512) -> dict:
+    rng = np.random.default_rng(seed)
+    lon, lat, t = satellite_tracks(slices, passes, per_pass, rng)
+    la, lo = np.radians(lat), np.radians(lon)
+    xyz = np.column_stack([np.cos(la) * np.cos(lo), np.cos(la) * np.sin(lo), np.sin(la)])
+    locs = np.column_stack([xyz, t])
+    covparms = (1.0, RHO_SPACE_5DEG, 3.0, 0.1)
+    scaled = np.column_stack([xyz / covparms[1], t / covparms[2]])
+    n = len(locs)
+    order = maxmin_exact(scaled) if n <= 20_000 else maxmin_approx(scaled, seed)
+    locs, scaled = locs[order], scaled[order]
+    NN = find_ordered_nn(scaled, m)
+    nu = 0.5
+    f = rff_field(scaled, nu, n_features, rng)
+    X = np.ones((n, 1))
+    y = 0.5 + math.sqrt(covparms[0]) * f + math.sqrt(covparms[0] * covparms[3]) * \
+        rng.standard_normal(n)
+    return _pack("satellite_spacetime", locs, NN, y, X, covparms, FAMILY_SPACETIME, nu, 3, m)
