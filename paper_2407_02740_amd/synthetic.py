@@ -86,7 +86,15 @@ def maxmin_approx(locs: np.ndarray, seed: int = 0) -> np.ndarray:
     for b in range(B * d):
         rev |= ((code >> b) & 1) << (B * d - 1 - b)
     tie = rng.random(n)
-    return np.lexsort((tie, rev))
+    # several points can share a cell: a cell's k-th point comes after every
+    # cell's (k-1)-th point, so each pass over the cells is coarse to fine
+    by_cell = np.lexsort((tie, rev))
+    sorted_rev = rev[by_cell]
+    start = np.r_[0, np.flatnonzero(np.diff(sorted_rev)) + 1]
+    rank_sorted = np.arange(n) - np.repeat(start, np.diff(np.r_[start, n]))
+    rank = np.empty(n, dtype=np.int64)
+    rank[by_cell] = rank_sorted
+    return np.lexsort((tie, rev, rank))
 
 
 # ----------------------------------------------------------------------------
