@@ -1,0 +1,171 @@
+/*
+ * vecchia.h -- C ABI of the MI355X (gfx950) Vecchia Gaussian-process library.
+ *
+ * Computes, for a Gaussian process observed at n ordered locations, the sums
+ * of Algorithm 1 of James & Guinness, "Implementation and Analysis of GPU
+ * Algorithms for Vecchia Approximation" (Section 3): for every observation i
+ * the conditional density of y_i given its at most m nearest previously
+ * ordered neighbours (the Vecchia factorisation, Section 2.1, Eq. 3) is
+ * formed from the (m+1) x (m+1) covariance of the neighbourhood, Cholesky
+ * factored, and its contributions to logdet, ySy, XSX, ySX, their covariance
+ * parameter derivatives and the Fisher information are summed over i.  A
+ * separate combine step (Section 3) turns the sums into the profile
+ * log-likelihood, gradient and Fisher information, and a Fisher-scoring
+ * update (Eq. 4) moves the covariance parameters.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every array argument is a DEVICE pointer owned by the caller.
+ *   The library allocates no device memory, keeps no per-call state and
+ *   never synchronises the stream: work is enqueued on `stream` (a
+ *   hipStream_t passed as void*, NULL = the default stream) and outputs are
+ *   valid once the stream has reached that point.
+ * Layouts (row-major, no padding):
+ *   locs[n][d]        FP64 coordinates (1 <= d <= 4).
+ *   NNarray[n][m+1]   int32, 0-based.  Row i holds i in column 0 and its
+ *                     q = min(i, m) conditioning neighbours in columns 1..q,
+ *                     each a previous observation (0 <= j < i), in any order;
+ *                     the remaining columns are ignored (-1 by convention).
+ *   y[n], X[n][p]     FP64 response and covariates (1 <= p <= 3).
+ *   covparms[P]       FP64 covariance parameters, read on the device:
+ *                       VEC_FAMILY_ISO        (sigma2, rho, tau2)          P = 3
+ *                       VEC_FAMILY_SPACETIME  (sigma2, rho_s, rho_t, tau2) P = 4
+ *                     Cov(a, b) = sigma2 * (f_nu(h) + tau2 * [a == b]) with
+ *                     h the range-scaled distance (space-time: the first
+ *                     nspace coordinates scaled by rho_s, the rest by rho_t),
+ *                     f_0.5 = e^-h, f_1.5 = (1+h) e^-h,
+ *                     f_2.5 = (1 + h + h^2/3) e^-h  (Section 4.3, Eq. 6 at
+ *                     nu = 0.5; tau2 is the nugget-to-variance ratio).
+ *   raw[nraw]         the sums, nraw = 2 + p*p + p + P*(2 + p*p + p) + P*P:
+ *                     [logdet, ySy, XSX[p][p], ySX[p], dlogdet[P], dySy[P],
+ *                      dXSX[P][p][p], dySX[P][p], ainfo[P][P]].
+ *   out[nout]         nout = 1 + P + P*P + p + p*p:
+ *                     [loglik, grad[P], info[P][P], betahat[p], betainfo[p][p]]
+ *                     with loglik = -1/2 (n log 2pi + logdet + ySy - ySX.betahat)
+ *                     (the paper's Eq. 1 is twice this), betahat = XSX^-1 ySX.
+ *   status[2]         int32 on the device: status[0] = OR of VEC_FLAG_*,
+ *                     status[1] = smallest observation index that raised a
+ *                     flag.  vec_status_clear() resets it.
+ * Errors.  Entry points return VEC_OK or a negative code.  Problems visible
+ *   on the host (null pointer, unsupported size, smoothness or family,
+ *   workspace too small) return VEC_EINVAL / VEC_EWORKSPACE before anything
+ *   is enqueued.  Problems found on the device (non positive-definite
+ *   neighbourhood covariance, malformed NNarray row, non-finite value) set
+ *   flags in `status`; outputs of that call are then undefined.  Read the
+ *   status after synchronising and decode it with vec_status_code().  HIP
+ *   launch failures return VEC_EHIP.  Calls that share a workspace or a
+ *   status word must not run concurrently on different streams.
+ */
+#ifndef VECCHIA_H
+#define VECCHIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VEC_OK 0
+#define VEC_EINVAL (-1)
+#define VEC_ENOTPD (-2)
+#define VEC_EBADNN (-3)
+#define VEC_ENONFINITE (-4)
+#define VEC_EHIP (-5)
+#define VEC_EWORKSPACE (-6)
+
+#define VEC_FLAG_NOTPD 1
+#define VEC_FLAG_BADNN 2
+#define VEC_FLAG_NONFINITE 4
+
+#define VEC_FAMILY_ISO 0
+#define VEC_FAMILY_SPACETIME 1
+
+typedef struct {
+  int64_t n;         /* number of observations (n >= 1, n < 2^31)          */
+  int32_t m;         /* neighbours per observation: NNarray has m+1 columns */
+  int32_t d;         /* coordinates per location, 1..4                     */
+  int32_t p;         /* covariates (columns of X), 1..3                    */
+  int32_t family;    /* VEC_FAMILY_ISO or VEC_FAMILY_SPACETIME             */
+  double smoothness; /* Matern smoothness nu: 0.5, 1.5 or 2.5 (fixed)      */
+  int32_t nspace;    /* space-time: leading spatial coordinates, 1..d-1    */
+  int32_t reserved;  /* must be 0                                          */
+} vec_problem;
+
+/* Number of covariance parameters P, raw sums, and combined outputs; a
+ * negative return means the problem description is invalid. */
+int vec_nparms(const vec_problem* pb);
+int vec_nraw(const vec_problem* pb);
+int vec_nout(const vec_problem* pb);
+
+/* Largest m the library accepts. */
+int vec_max_m(void);
+
+/* Bytes of device workspace vec_raw_sums needs for the observation range
+ * [i0, i1) on the current device (0 if the problem is invalid). */
+size_t vec_workspace_bytes(const vec_problem* pb, int64_t i0, int64_t i1);
+
+/* Sums of Algorithm 1 (Section 3) over observations i0 <= i < i1 into
+ * raw[nraw] (overwritten; zeros for an empty range).  `workspace` holds at
+ * least vec_workspace_bytes(pb, i0, i1) bytes of device memory, 8-byte
+ * aligned, whose contents on entry do not matter.  The result is
+ * deterministic for a fixed device, problem and range. */
+int vec_raw_sums(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                 const double* y, const double* X, const double* covparms, int64_t i0,
+                 int64_t i1, double* raw, void* workspace, size_t workspace_bytes,
+                 int32_t* status, void* stream);
+
+/* The fused per-neighbourhood kernel alone: the sums of observations
+ * [i0, i1) split into *nblocks rows of partial sums, partials[*nblocks][nraw]
+ * (any summation order of the rows gives the raw sums).  `partials` holds at
+ * least vec_workspace_bytes(pb, i0, i1) bytes of device memory; *nblocks is
+ * written on the host (0 for an empty range).  For callers that reduce
+ * partial sums themselves, e.g. across devices that each own a range of
+ * observations. */
+int vec_block_sums(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                   const double* y, const double* X, const double* covparms, int64_t i0,
+                   int64_t i1, double* partials, size_t partials_bytes, int32_t* nblocks,
+                   int32_t* status, void* stream);
+
+/* The "separate function" of Section 3: raw sums of the whole problem (all
+ * n observations) to out[nout].  A singular XSX sets VEC_FLAG_NONFINITE. */
+int vec_combine(const vec_problem* pb, const double* raw, double* out, int32_t* status,
+                void* stream);
+
+/* vec_raw_sums over all n observations followed by vec_combine. */
+int vec_loglik_grad_info(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                         const double* y, const double* X, const double* covparms, double* raw,
+                         double* out, void* workspace, size_t workspace_bytes, int32_t* status,
+                         void* stream);
+
+/* One Fisher-scoring step, Eq. (4), on phi = log(covparms):
+ * g = covparms .* grad, I = diag(covparms) info diag(covparms),
+ * step = I^-1 g scaled to length max_step if longer, covparms *= exp(step).
+ * Reads grad and info from out[]; updates covparms in place on the device.
+ * Nothing is changed if status already holds a flag or I is not positive
+ * definite (the latter sets VEC_FLAG_NONFINITE). */
+int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms,
+                      int32_t* status, double max_step, void* stream);
+
+/* `iters` Fisher-scoring iterations (evaluate, reduce, combine, update), all
+ * on the device.  With use_graph != 0 one iteration is captured once as a
+ * HIP graph and replayed; otherwise the kernels are launched directly.
+ * covparms is updated in place, out[] holds the last evaluation (taken at
+ * the parameters before the last update). */
+int vec_fisher_fit(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                   const double* y, const double* X, double* covparms, int32_t iters,
+                   double max_step, double* raw, double* out, void* workspace,
+                   size_t workspace_bytes, int32_t* status, int32_t use_graph, void* stream);
+
+/* Reset status to "no flag" (a kernel, safe inside graph capture). */
+int vec_status_clear(int32_t* status, void* stream);
+
+/* Map a status word copied to the host to a return code (VEC_OK or the
+ * most severe of VEC_EBADNN, VEC_ENOTPD, VEC_ENONFINITE). */
+int vec_status_code(const int32_t* host_status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VECCHIA_H */

@@ -1,0 +1,240 @@
+"""Thin Python binding of libvecchia.so (include/vecchia.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch provides device memory and the stream.  If
+the library has not been built this module raises on first use; there is no
+CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvecchia.so")
+
+VEC_OK, VEC_EINVAL, VEC_ENOTPD, VEC_EBADNN, VEC_ENONFINITE, VEC_EHIP, VEC_EWORKSPACE = \
+    0, -1, -2, -3, -4, -5, -6
+FAMILY_ISO, FAMILY_SPACETIME = 0, 1
+ERRORS = {VEC_EINVAL: "invalid argument", VEC_ENOTPD: "covariance not positive definite",
+          VEC_EBADNN: "malformed NNarray row", VEC_ENONFINITE: "non-finite value",
+          VEC_EHIP: "HIP runtime error", VEC_EWORKSPACE: "workspace too small"}
+
+
+class VecchiaError(RuntimeError):
+    def __init__(self, code: int, where: str = "", bad_i: int | None = None):
+        msg = f"{where}: {ERRORS.get(code, code)}"
+        if bad_i is not None:
+            msg += f" (first at observation {bad_i})"
+        super().__init__(msg)
+        self.code = code
+        self.bad_i = bad_i
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("family", ctypes.c_int32), ("smoothness", ctypes.c_double),
+                ("nspace", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2407_02740_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        pp = ctypes.POINTER(Problem)
+        for name in ("vec_nparms", "vec_nraw", "vec_nout"):
+            getattr(L, name).restype = ctypes.c_int
+            getattr(L, name).argtypes = [pp]
+        L.vec_max_m.restype = ctypes.c_int
+        L.vec_max_m.argtypes = []
+        L.vec_workspace_bytes.restype = ctypes.c_size_t
+        L.vec_workspace_bytes.argtypes = [pp, ctypes.c_int64, ctypes.c_int64]
+        L.vec_raw_sums.restype = ctypes.c_int
+        L.vec_raw_sums.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int64,
+                                   _VP, _VP, ctypes.c_size_t, _VP, _VP]
+        L.vec_block_sums.restype = ctypes.c_int
+        L.vec_block_sums.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int64,
+                                     _VP, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32), _VP, _VP]
+        L.vec_combine.restype = ctypes.c_int
+        L.vec_combine.argtypes = [pp, _VP, _VP, _VP, _VP]
+        L.vec_loglik_grad_info.restype = ctypes.c_int
+        L.vec_loglik_grad_info.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                           ctypes.c_size_t, _VP, _VP]
+        L.vec_fisher_update.restype = ctypes.c_int
+        L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
+        L.vec_fisher_fit.restype = ctypes.c_int
+        L.vec_fisher_fit.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_double,
+                                     _VP, _VP, _VP, ctypes.c_size_t, _VP, ctypes.c_int32, _VP]
+        L.vec_status_clear.restype = ctypes.c_int
+        L.vec_status_clear.argtypes = [_VP, _VP]
+        L.vec_status_code.restype = ctypes.c_int
+        L.vec_status_code.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != VEC_OK:
+        raise VecchiaError(rc, where)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def nparms(family: int) -> int:
+    return {FAMILY_ISO: 3, FAMILY_SPACETIME: 4}[family]
+
+
+def nraw(p: int, P: int) -> int:
+    return 2 + p * p + p + P * (2 + p * p + p) + P * P
+
+
+def unpack_out(out, p: int, P: int) -> dict:
+    """Split out[nout] = [loglik, grad[P], info[P][P], betahat[p], betainfo[p][p]]."""
+    o = out.detach().double().cpu().numpy() if isinstance(out, torch.Tensor) else out
+    return dict(loglik=float(o[0]), grad=o[1:1 + P].copy(),
+                info=o[1 + P:1 + P + P * P].reshape(P, P).copy(),
+                betahat=o[1 + P + P * P:1 + P + P * P + p].copy(),
+                betainfo=o[1 + P + P * P + p:].reshape(p, p).copy())
+
+
+class Vecchia:
+    """Device-resident problem: inputs copied to the GPU once, then evaluated
+    by the library entry points on the current torch stream."""
+
+    def __init__(self, locs, NN, y, X, family: int = FAMILY_ISO, smoothness: float = 0.5,
+                 nspace: int = 0, device: str = "cuda"):
+        def f64(a):
+            return torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
+
+        self.locs = f64(locs)
+        if self.locs.dim() == 1:
+            self.locs = self.locs[:, None].contiguous()
+        self.NN = torch.as_tensor(NN, dtype=torch.int32).contiguous().to(device)
+        self.y = f64(y)
+        self.X = f64(X)
+        if self.X.dim() == 1:
+            self.X = self.X[:, None].contiguous()
+        n, d = self.locs.shape
+        self.pb = Problem(n=n, m=self.NN.shape[1] - 1, d=d, p=self.X.shape[1], family=family,
+                          smoothness=float(smoothness), nspace=int(nspace), reserved=0)
+        L = lib()
+        self.P = L.vec_nparms(ctypes.byref(self.pb))
+        if self.P < 0:
+            raise VecchiaError(VEC_EINVAL, "problem description")
+        self.p = self.pb.p
+        self.n = n
+        self.nraw = L.vec_nraw(ctypes.byref(self.pb))
+        self.nout = L.vec_nout(ctypes.byref(self.pb))
+        self.device = self.y.device
+        self.status = torch.zeros(2, dtype=torch.int32, device=self.device)
+        self.raw = torch.zeros(self.nraw, dtype=torch.float64, device=self.device)
+        self.out = torch.zeros(self.nout, dtype=torch.float64, device=self.device)
+        self._ws = None
+        self.clear_status()
+
+    # -- helpers ------------------------------------------------------------
+    def workspace(self, i0: int = 0, i1: int | None = None) -> torch.Tensor:
+        i1 = self.n if i1 is None else i1
+        nb = lib().vec_workspace_bytes(ctypes.byref(self.pb), i0, i1)
+        if nb == 0:
+            raise VecchiaError(VEC_EINVAL, "vec_workspace_bytes")
+        if self._ws is None or self._ws.numel() * 8 < nb:
+            self._ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        return self._ws
+
+    def covparms(self, covparms) -> torch.Tensor:
+        t = torch.as_tensor(covparms, dtype=torch.float64).to(self.device).contiguous()
+        if t.numel() != self.P:
+            raise ValueError(f"covparms needs {self.P} entries")
+        return t
+
+    def clear_status(self):
+        _check(lib().vec_status_clear(_dev(self.status, torch.int32, "status"), _stream()),
+               "vec_status_clear")
+
+    def check_status(self, where: str = "device"):
+        host = self.status.cpu()
+        arr = (ctypes.c_int32 * 2)(int(host[0]), int(host[1]))
+        rc = lib().vec_status_code(arr)
+        if rc != VEC_OK:
+            raise VecchiaError(rc, where, int(host[1]))
+
+    # -- entry points ---------------------------------------------------------
+    def raw_sums(self, covparms, i0: int = 0, i1: int | None = None, check: bool = True):
+        i1 = self.n if i1 is None else i1
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        ws = self.workspace(i0, i1)
+        _check(lib().vec_raw_sums(ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(),
+                                  self.y.data_ptr(), self.X.data_ptr(),
+                                  _dev(cp, torch.float64, "covparms"), i0, i1,
+                                  self.raw.data_ptr(), ws.data_ptr(), ws.numel() * 8,
+                                  self.status.data_ptr(), _stream()), "vec_raw_sums")
+        if check:
+            self.check_status("vec_raw_sums")
+        return self.raw
+
+    def block_sums(self, covparms: torch.Tensor, i0: int = 0, i1: int | None = None) -> int:
+        """Launch the fused kernel alone; returns the number of partial rows
+        written to the workspace (no status check, no synchronisation)."""
+        i1 = self.n if i1 is None else i1
+        ws = self.workspace(i0, i1)
+        nb = ctypes.c_int32(0)
+        _check(lib().vec_block_sums(ctypes.byref(self.pb), self.locs.data_ptr(),
+                                    self.NN.data_ptr(), self.y.data_ptr(), self.X.data_ptr(),
+                                    _dev(covparms, torch.float64, "covparms"), i0, i1,
+                                    ws.data_ptr(), ws.numel() * 8, ctypes.byref(nb),
+                                    self.status.data_ptr(), _stream()), "vec_block_sums")
+        return nb.value
+
+    def loglik_grad_info(self, covparms, check: bool = True):
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        ws = self.workspace()
+        _check(lib().vec_loglik_grad_info(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), self.raw.data_ptr(),
+            self.out.data_ptr(), ws.data_ptr(), ws.numel() * 8, self.status.data_ptr(), _stream()),
+            "vec_loglik_grad_info")
+        if check:
+            self.check_status("vec_loglik_grad_info")
+        return self.out
+
+    def fisher_update(self, covparms: torch.Tensor, max_step: float = 1.0):
+        _check(lib().vec_fisher_update(ctypes.byref(self.pb), self.out.data_ptr(),
+                                       _dev(covparms, torch.float64, "covparms"),
+                                       self.status.data_ptr(), float(max_step), _stream()),
+               "vec_fisher_update")
+        return covparms
+
+    def fisher_fit(self, covparms: torch.Tensor, iters: int, use_graph: bool = True,
+                   max_step: float = 1.0, check: bool = True):
+        ws = self.workspace()
+        _check(lib().vec_fisher_fit(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(covparms, torch.float64, "covparms"), int(iters),
+            float(max_step), self.raw.data_ptr(), self.out.data_ptr(), ws.data_ptr(),
+            ws.numel() * 8, self.status.data_ptr(), int(bool(use_graph)), _stream()),
+            "vec_fisher_fit")
+        if check:
+            self.check_status("vec_fisher_fit")
+        return covparms
