@@ -12,6 +12,10 @@
 
 namespace vecchia {
 
+#ifdef VECCHIA_SECTION_TIMING
+__device__ unsigned long long section_cycles[kSections];
+#endif
+
 // Instantiations live in vecchia_inst_k*.hip (compiled in parallel).
 #define VEC_DECLARE(K, PC, NG)                                                                 \
   extern template hipError_t launch_sums<K, PC, NG>(                                           \
@@ -403,5 +407,17 @@ int vec_fisher_fit(const vec_problem* pb, const double* locs, const int32_t* NNa
   hipGraphDestroy(graph);
   return hip_code(e);
 }
+
+#ifdef VECCHIA_SECTION_TIMING
+// Profiling build only: copy out and reset the per-section cycle counters.
+int vec_debug_section_cycles(unsigned long long* host_out, int n) {
+  if (n > kSections) n = kSections;
+  if (hipMemcpyFromSymbol(host_out, HIP_SYMBOL(section_cycles), n * sizeof(unsigned long long)) !=
+      hipSuccess)
+    return VEC_EHIP;
+  unsigned long long zero[kSections] = {};
+  return hip_code(hipMemcpyToSymbol(HIP_SYMBOL(section_cycles), zero, sizeof(zero)));
+}
+#endif
 
 }  // extern "C"

@@ -56,6 +56,42 @@
 
 namespace vecchia {
 
+#ifdef VECCHIA_ISA_MARKS
+#define VEC_MARK(x) asm volatile(";@@ " x)
+#else
+#define VEC_MARK(x)
+#endif
+
+// Profiling build only (-DVECCHIA_SECTION_TIMING): shader-clock cycles
+// spent in each section of the per-neighbourhood loop, summed over waves.
+#ifdef VECCHIA_SECTION_TIMING
+constexpr int kSections = 12;
+extern __device__ unsigned long long section_cycles[kSections];
+#define VEC_TDECL                                  \
+  __shared__ unsigned long long tsec_[kSections];  \
+  if (threadIdx.x < kSections) tsec_[threadIdx.x] = 0; \
+  unsigned long long tlast_ = clock64();           \
+  int tcur_ = 0;
+#define VEC_TMARK(idx)                                   \
+  do {                                                   \
+    __builtin_amdgcn_sched_barrier(0);                   \
+    const unsigned long long tnow_ = clock64();          \
+    if (threadIdx.x == 0) tsec_[tcur_] += tnow_ - tlast_; \
+    tlast_ = tnow_;                                      \
+    tcur_ = (idx);                                       \
+  } while (0)
+#define VEC_TFLUSH                                                      \
+  do {                                                                  \
+    VEC_TMARK(0);                                                       \
+    __syncthreads();                                                    \
+    if (threadIdx.x < kSections) atomicAdd(&section_cycles[threadIdx.x], tsec_[threadIdx.x]); \
+  } while (0)
+#else
+#define VEC_TDECL
+#define VEC_TMARK(idx)
+#define VEC_TFLUSH
+#endif
+
 constexpr int kGroupsPerBlock = 4;
 constexpr int kThreads = 64;
 
@@ -73,12 +109,12 @@ __device__ __forceinline__ void sfor(F&& f) {
 // Value of x held by lane LANE of this lane's 16-lane DPP row.
 template <int LANE>
 __device__ __forceinline__ double bcast(double x) {
-  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + LANE, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + LANE, 0xF, 0xF, false);
 }
 
 template <int CTRL>
 __device__ __forceinline__ double dpp(double x) {
-  return __builtin_amdgcn_update_dpp(0.0, x, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
 }
 
 // Sum over the 16 lanes of the DPP row, identical bits on every lane:
@@ -118,20 +154,51 @@ struct Geo {
 
 __device__ __forceinline__ int row_of(int s, int l) { return 16 * s + ((s & 1) ? 15 - l : l); }
 
-// h = sqrt(h2) and 1/h, both 0 at h2 = 0.
+// e^-h for h >= 0 (very large h gives 0).  Cody-Waite reduction
+// -h = n ln2 + r, |r| <= ln2/2, with ln2 split into a 32-significant-bit
+// head (n * head is exact for |n| < 2^20) and the remaining tail; e^r by
+// its Taylor series to degree 13 (truncation below 5e-18 relative); 2^n by
+// ldexp.  Arguments below -800 are clamped: 2^-1154 underflows to 0.
+__host__ __device__ __forceinline__ double exp_neg(double h) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+  const double x = fmax(-h, -800.0);
+  const double n = rint(x * kLog2e);
+  double r = __builtin_fma(-n, kLn2Hi, x);
+  r = __builtin_fma(-n, kLn2Lo, r);
+  double p = 1.0 / 6227020800.0;                  // 1/13!
+  p = __builtin_fma(p, r, 1.0 / 479001600.0);     // 1/12!
+  p = __builtin_fma(p, r, 1.0 / 39916800.0);      // 1/11!
+  p = __builtin_fma(p, r, 1.0 / 3628800.0);       // 1/10!
+  p = __builtin_fma(p, r, 1.0 / 362880.0);        // 1/9!
+  p = __builtin_fma(p, r, 1.0 / 40320.0);         // 1/8!
+  p = __builtin_fma(p, r, 1.0 / 5040.0);          // 1/7!
+  p = __builtin_fma(p, r, 1.0 / 720.0);           // 1/6!
+  p = __builtin_fma(p, r, 1.0 / 120.0);           // 1/5!
+  p = __builtin_fma(p, r, 1.0 / 24.0);            // 1/4!
+  p = __builtin_fma(p, r, 1.0 / 6.0);             // 1/3!
+  p = __builtin_fma(p, r, 0.5);                   // 1/2!
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
+// h = sqrt(h2) and 1/h.  1e-300 is added to h2 so that coincident
+// locations give h ~ 1e-150 and a finite 1/h (every use multiplies 1/h by a
+// squared coordinate difference that is then 0); for any h2 above 1e-284 the
+// addition does not change h2.
 __device__ __forceinline__ void dist_from_sq(double h2, double& h, double& hinv) {
-  const bool pos = h2 > 0.0;
-  const double r = rsqrt_refined(pos ? h2 : 1.0);
-  h = pos ? h2 * r : 0.0;
-  hinv = pos ? r : 0.0;
+  const double x = h2 + 1e-300;
+  const double r = rsqrt_refined(x);
+  h = x * r;
+  hinv = r;
 }
 
 struct CovCoef {
   double sigma2, diag;  // sigma2, sigma2 * (1 + tau2)
   double c1, c2;        // f = (1 + c1 h + c2 h^2) e^-h
   double a0, a1, a2;    // -f'(h)/h = (a0 + a1 h + a2/h) e^-h
-  double irk[4];        // per-coordinate 1/range
-  double msk[4];        // 1 for coordinates of the second range group
   double ir[2];         // 1/range per group
 };
 
@@ -148,20 +215,32 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   constexpr int P = NG + 2;   // sigma2, ranges, tau2
   constexpr int NR = NG + 1;  // parameters whose w has entries above the self row
   constexpr int NRAW = nraw_of(PC, P);
-  constexpr int LPN = K * (K + 1) / 2;
+  constexpr int LPN = K * (K - 1) / 2;  // strictly lower L, index r(r-1)/2 + c
   constexpr int SS = G::slot_of(K - 1);
   constexpr int LS = G::lane_of(K - 1);
   constexpr int NGR = NR * (NR + 1) / 2;
   constexpr int NPART = NR + NR * PC + NGR;
 
-  __shared__ double zs[kGroupsPerBlock][KP][4];
+  // per-row record: scaled coordinates z[0..3] (space-time: time in z[3])
+  // and u; the products g_rho = dSigma/drho u live in their own array so
+  // that reads of rec never wait behind the ds_add_f64 into g
+  constexpr int RZ = 0, RU = 4;
+  constexpr int RS = 6;  // row stride, 16-byte aligned
+  __shared__ double rec[kGroupsPerBlock][KP][RS];
+  __shared__ double gvec[kGroupsPerBlock][KP][NG];
   __shared__ double Lp[kGroupsPerBlock][LPN];
-  __shared__ double uv[kGroupsPerBlock][KP];
-  __shared__ double gv[kGroupsPerBlock][NG][KP];
   __shared__ double acc[kGroupsPerBlock][NRAW];
+  // running product of conditional variances (mantissa, exponent)
+  __shared__ double vprod[kGroupsPerBlock][2];
+  // per strictly-lower pair (r, c), index r(r-1)/2 + c: sigma2 (-f'(h)/h),
+  // from which every range derivative of the pair follows (last slot: sink
+  // for diagonal entries)
+  constexpr int NPAIR = KP * (KP - 1) / 2;
+  __shared__ double sfv[kGroupsPerBlock][NPAIR + 1];
 
-  const int l = threadIdx.x & 15;
+  const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
+  constexpr double kFar = 1e30;
 
   CovCoef cf;
   cf.sigma2 = covparms[0];
@@ -174,57 +253,73 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   cf.a0 = (nu == 0) ? 0.0 : ((nu == 1) ? 1.0 : 1.0 / 3.0);
   cf.a1 = (nu == 2) ? 1.0 / 3.0 : 0.0;
   cf.a2 = (nu == 0) ? 1.0 : 0.0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const bool g1 = (NG == 2) && (k >= nspace);
-    cf.irk[k] = g1 ? cf.ir[1] : cf.ir[0];
-    cf.msk[k] = g1 ? 1.0 : 0.0;
-  }
   const double inv_sigma2 = 1.0 / cf.sigma2;
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
+  if (threadIdx.x < kGroupsPerBlock) {
+    vprod[threadIdx.x][0] = 1.0;
+    vprod[threadIdx.x][1] = 0.0;
+  }
 
+  VEC_TDECL
   const int64_t total = i1 - i0;
   for (int64_t base = (int64_t)blockIdx.x * kGroupsPerBlock; base < total;
        base += (int64_t)gridDim.x * kGroupsPerBlock) {
+    // an opaque copy of the lane id per iteration keeps the many
+    // lane-dependent predicates from being hoisted out of the loop
+    int l = lane;
+    asm volatile("" : "+v"(l));
     const bool active = base + grp < total;
     const int64_t i = i0 + (active ? base + grp : total - 1);
     const int q = (int)(i < (int64_t)m ? i : (int64_t)m);
     const int32_t* nnrow = NN + i * (int64_t)(m + 1);
     bool badnn = false;
+    bool badval = false;
 
+    VEC_MARK("gather");
+    VEC_TMARK(1);
     // ---------------- gather ----------------
-    int kind[NS];  // 0 neighbour, 1 padding, 2 self, 3 beyond K
+    // Rows without an observation (padding q <= r < K-1, rows >= K) get
+    // coordinates kFar*(1+r) apart from everything: their covariance with
+    // any other row is exp(-h) = 0 exactly, so the padding block decouples
+    // with no masking anywhere below.
     double zo[NS][4];
     double rhs[1 + PC][NS];
     if (l == LS) badnn |= (nnrow[0] != (int32_t)i);
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
-      int kd = 1;
       int64_t id = -1;
-      if (r >= K) {
-        kd = 3;
-      } else if (r == K - 1) {
-        kd = 2;
+      if (r == K - 1) {
         id = i;
       } else if (r < q) {
         const int64_t j = nnrow[1 + r];
-        if (j < 0 || j >= i) {
+        if (j < 0 || j >= i)
           badnn = true;
-        } else {
-          kd = 0;
+        else
           id = j;
-        }
       }
-      kind[s] = kd;
       const bool has = id >= 0;
       const int64_t ids = has ? id : i;  // always a valid row for the loads
+      // isotropic: coordinate k in z[k]; space-time: spatial coordinates
+      // 0..d-2 in z[0..d-2] scaled by 1/rho_s, time (coordinate d-1) in z[3]
+      // scaled by 1/rho_t
+      double zc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double v = (k < d) ? locs[ids * d + k] : 0.0;
-        zo[s][k] = has ? v * cf.irk[k] : 0.0;
-        zs[grp][r][k] = zo[s][k];
+        if (k < d) {
+          const double v = locs[ids * d + k];
+          badval |= !__builtin_isfinite(v);
+          if (NG == 2 && k == d - 1)
+            zc[3] = v * cf.ir[1];
+          else
+            zc[k] = v * cf.ir[0];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        zo[s][k] = has ? zc[k] : ((k == 0) ? kFar * (double)(1 + r) : 0.0);
+        rec[grp][r][RZ + k] = zo[s][k];
       }
       rhs[0][s] = has ? y[ids] : 0.0;
 #pragma unroll
@@ -232,8 +327,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     });
     __syncthreads();
 
-    // off-diagonal covariance of two scaled locations
-    auto cov_off = [&](const double* za, const double* zb) -> double {
+    // covariance of two distinct scaled locations, and the pair's range
+    // derivative factor sigma2 (-f'(h)/h) stored at sfv[idx]
+    auto pair_eval = [&](const double* za, const double* zb, int idx) -> double {
       double h2 = 0.0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -242,16 +338,20 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       }
       double h, hinv;
       dist_from_sq(h2, h, hinv);
-      const double E = exp(-h);
-      return cf.sigma2 * __builtin_fma(h, __builtin_fma(h, cf.c2, cf.c1), 1.0) * E;
+      const double sE = cf.sigma2 * exp_neg(h);
+      const double sF = sE * __builtin_fma(cf.a1, h, __builtin_fma(cf.a2, hinv, cf.a0));
+      sfv[grp][idx] = (NG == 1) ? sF * h2 * cf.ir[0] : sF;
+      return sE * __builtin_fma(h, __builtin_fma(h, cf.c2, cf.c1), 1.0);
     };
+    auto pidx = [](int r, int c) { return r * (r - 1) / 2 + c; };
 
+    VEC_MARK("phase1");
+    VEC_TMARK(2);
     // ---------------- phase 1: covariance ----------------
+    // Entries above the diagonal of a lane's rows are never read, so every
+    // step may write its value into both candidate registers.
     double A[NL];
     sfor<0, NL>([&](auto e_) { A[e_.value] = 0.0; });
-    bool realr[NS];
-    sfor<0, NS>([&](auto s_) { realr[s_.value] = (kind[s_.value] == 0) || (kind[s_.value] == 2); });
-
     // off-diagonal 16x16 blocks: slot s rows x columns of block t < s
     sfor<1, NS>([&](auto s_) {
       constexpr int s = s_.value;
@@ -261,9 +361,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
           constexpr int c = 16 * t + cc_.value;
           double zc[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) zc[k] = zs[grp][c][k];
-          const double v = cov_off(zo[s], zc);
-          A[G::off(s) + c] = (realr[s] && (c < q)) ? v : 0.0;
+          for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
+          A[G::off(s) + c] = pair_eval(zo[s], zc, pidx(row_of(s, l), c));
         });
       });
     });
@@ -275,40 +374,38 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         constexpr int u = u_.value;
         const bool first = (u <= l);
         const int c = first ? 16 * s0 + u : 16 * s1 + 16 - u;
-        const int r = first ? row_of(s0, l) : row_of(s1, l);
-        const bool rr = first ? realr[s0] : realr[s1];
+        const int r = first ? 16 * s0 + l : 16 * s1 + 15 - l;
         double zr[4], zc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          zr[k] = first ? zo[s0][k] : zo[s1][k];
-          zc[k] = zs[grp][c][k];
+          zr[k] = rec[grp][r][RZ + k];
+          zc[k] = rec[grp][c][RZ + k];
         }
-        const bool rc = (c < q) || (c == K - 1);
-        const double off = cov_off(zr, zc);
-        const double v = (c == r) ? (rr ? cf.diag : 1.0) : ((rr && rc) ? off : 0.0);
-        if constexpr (u <= 15) A[G::off(s0) + 16 * s0 + u] = first ? v : A[G::off(s0) + 16 * s0 + u];
-        if constexpr (u >= 1 && 16 * s1 + 16 - u < K)
-          A[G::off(s1) + 16 * s1 + 16 - u] = first ? A[G::off(s1) + 16 * s1 + 16 - u] : v;
+        const double off = pair_eval(zr, zc, (c == r) ? NPAIR : pidx(r, c));
+        const double v = (c == r) ? cf.diag : off;
+        if constexpr (u <= 15) A[G::off(s0) + 16 * s0 + u] = v;
+        if constexpr (u >= 1 && 16 * s1 + 16 - u < K) A[G::off(s1) + 16 * s1 + 16 - u] = v;
       });
     });
     // unpaired last slot (odd NS): its triangle directly
     if constexpr (NS & 1) {
       constexpr int s = NS - 1;
       sfor<0, G::len(s) - 16 * s>([&](auto u_) {
-        constexpr int u = u_.value;
-        constexpr int c = 16 * s + u;
+        constexpr int c = 16 * s + u_.value;
         const int r = row_of(s, l);
         double zc[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) zc[k] = zs[grp][c][k];
-        const bool rc = (c < q) || (c == K - 1);
-        const double off = cov_off(zo[s], zc);
-        const double v = (c == r) ? (realr[s] ? cf.diag : 1.0) : ((realr[s] && rc) ? off : 0.0);
-        A[G::off(s) + c] = (u <= l) ? v : 0.0;
+        for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
+        const double off = pair_eval(zo[s], zc, (c < r) ? pidx(r, c) : NPAIR);
+        A[G::off(s) + c] = (c == r) ? cf.diag : off;
       });
     }
 
+    VEC_MARK("cholesky");
+    VEC_TMARK(3);
     // ---------------- Cholesky (right-looking, in registers) ----------------
+    // Scaling column c by 1/sqrt(pivot) turns the pivot entry itself into
+    // sqrt(pivot); only the owner of row c keeps 1/L_cc (idg).
     double idg[NS];
     sfor<0, NS>([&](auto s_) { idg[s_.value] = 0.0; });
     bool notpd = false;
@@ -320,16 +417,12 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       const double dv = bcast<lc>(A[G::off(sc) + c]);
       notpd |= !(dv > 0.0);
       const double rs = rsqrt_refined(dv);
-      const double pv = dv * rs;
       if constexpr (c == K - 1) vself = dv;
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (16 * s + 15 >= c) {
-          const int r = row_of(s, l);
-          A[G::off(s) + c] = (r == c) ? pv : A[G::off(s) + c] * rs;
-          idg[s] = (r == c) ? rs : idg[s];
-        }
+        if constexpr (16 * s + 15 >= c) A[G::off(s) + c] *= rs;
       });
+      idg[sc] = (row_of(sc, l) == c) ? rs : idg[sc];
       sfor<c + 1, K>([&](auto r_) {
         constexpr int r = r_.value;
         constexpr int sr = r / 16;
@@ -342,6 +435,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         });
       });
     });
+    VEC_MARK("zero_upper");
+    VEC_TMARK(4);
     // keep only the strict lower triangle (diagonal lives in idg as 1/L_rr)
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
@@ -373,15 +468,19 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         sfor<0, NS>([&](auto s_) { x[v_.value][s_.value] *= idg[s_.value]; });
       });
     };
+    VEC_MARK("fwd_rhs");
+    VEC_TMARK(5);
     fwd(rhs);  // Liy, LiX
 
+    VEC_MARK("backsolve");
+    VEC_TMARK(6);
     // ---------------- u = L^{-T} e_last via L in LDS ----------------
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
       sfor<0, G::len(s)>([&](auto c_) {
         constexpr int c = c_.value;
-        if (c < r && r < K) Lp[grp][r * (r + 1) / 2 + c] = A[G::off(s) + c];
+        if (c < r && r < K) Lp[grp][r * (r - 1) / 2 + c] = A[G::off(s) + c];
       });
     });
     double uu[NS];
@@ -397,9 +496,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         if constexpr (16 * s < r) {
           const int row = row_of(s, l);
           if constexpr (16 * s + 15 < r) {
-            uu[s] = __builtin_fma(-Lp[grp][r * (r + 1) / 2 + row], ur, uu[s]);
+            uu[s] = __builtin_fma(-Lp[grp][r * (r - 1) / 2 + row], ur, uu[s]);
           } else {
-            const double lv = Lp[grp][r * (r + 1) / 2 + (row < r ? row : r)];
+            const double lv = Lp[grp][r * (r - 1) / 2 + (row < r ? row : r - 1)];
             uu[s] = (row < r) ? __builtin_fma(-lv, ur, uu[s]) : uu[s];
           }
         }
@@ -410,69 +509,81 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       uu[s] *= idg[s];
       const int r = row_of(s, l);
       if (r < K) {
-        uv[grp][r] = uu[s];
+        rec[grp][r][RU] = uu[s];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) gv[grp][g][r] = 0.0;
+        for (int g = 0; g < NG; ++g) gvec[grp][r][g] = 0.0;
       }
     });
     __syncthreads();
 
+    VEC_MARK("phase2");
+    VEC_TMARK(7);
     // ---------------- phase 2: g_rho = dSigma/drho * u (tournament) ----------------
+    // Pairs with a padding row have exp(-h) = 0 and add nothing.
     {
       constexpr int KO = (K & 1) ? K : K + 1;
       constexpr int M2 = (KO - 1) / 2;
       constexpr int NSUB = (M2 + 15) / 16;
-      for (int t = 0; t < KO; ++t) {
+      sfor<0, KO>([&](auto t_) {
+        constexpr int t = t_.value;
         sfor<0, NSUB>([&](auto j_) {
           const int sidx = 1 + l + 16 * j_.value;
           int a = t + sidx;
           a -= (a >= KO) ? KO : 0;
           int b = t - sidx;
           b += (b < 0) ? KO : 0;
-          const bool ra = (a < q) || (a == K - 1);
-          const bool rb = (b < q) || (b == K - 1);
-          if (sidx <= M2 && ra && rb) {
-            double h2 = 0.0, h2g1 = 0.0;
+          if (sidx <= M2 && (KO == K || (a < K && b < K))) {
+            const int hi = a > b ? a : b, lo = a > b ? b : a;
+            const double sF = sfv[grp][pidx(hi, lo)];
+            const double* ra = rec[grp][a];
+            const double* rb = rec[grp][b];
+            double* ga = gvec[grp][a];
+            double* gb = gvec[grp][b];
+            const double ua = ra[RU], ub = rb[RU];
+            if constexpr (NG == 1) {
+              // stored directly as dSigma/drho for the isotropic family
+              atomicAdd(&ga[0], sF * ub);
+              atomicAdd(&gb[0], sF * ua);
+            } else {
+              double h2s = 0.0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const double dz = zs[grp][a][k] - zs[grp][b][k];
-              const double dz2 = dz * dz;
-              h2 += dz2;
-              h2g1 = __builtin_fma(cf.msk[k], dz2, h2g1);
-            }
-            double h, hinv;
-            dist_from_sq(h2, h, hinv);
-            const double E = exp(-h);
-            const double sF =
-                cf.sigma2 * E * __builtin_fma(cf.a1, h, __builtin_fma(cf.a2, hinv, cf.a0));
-            const double ua = uv[grp][a], ub = uv[grp][b];
-            const double D0 = sF * ((NG == 2) ? (h2 - h2g1) : h2) * cf.ir[0];
-            atomicAdd(&gv[grp][0][a], D0 * ub);
-            atomicAdd(&gv[grp][0][b], D0 * ua);
-            if constexpr (NG == 2) {
-              const double D1 = sF * h2g1 * cf.ir[1];
-              atomicAdd(&gv[grp][1][a], D1 * ub);
-              atomicAdd(&gv[grp][1][b], D1 * ua);
+              for (int k = 0; k < 3; ++k) {
+                const double dz = ra[RZ + k] - rb[RZ + k];
+                h2s = __builtin_fma(dz, dz, h2s);
+              }
+              const double dt = ra[RZ + 3] - rb[RZ + 3];
+              const double D0 = sF * h2s * cf.ir[0];
+              const double D1 = sF * (dt * dt) * cf.ir[1];
+              atomicAdd(&ga[0], D0 * ub);
+              atomicAdd(&gb[0], D0 * ua);
+              atomicAdd(&ga[1], D1 * ub);
+              atomicAdd(&gb[1], D1 * ua);
             }
           }
         });
-      }
+      });
     }
     __syncthreads();
 
+    VEC_MARK("w_solve");
+    VEC_TMARK(8);
     // ---------------- w = L^{-1} (dSigma_j u) ----------------
+    // range parameters: g_rho from phase 2; tau2: dSigma = sigma2 I, so
+    // w_tau2 = sigma2 L^{-1} u (one more forward solve)
     double w[NR][NS];
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
       const int rc = r < K ? r : K - 1;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) w[g][s] = (r < K) ? gv[grp][g][rc] : 0.0;
+      for (int g = 0; g < NG; ++g) w[g][s] = (r < K) ? gvec[grp][rc][g] : 0.0;
       w[NG][s] = uu[s];
     });
     fwd(w);
     sfor<0, NS>([&](auto s_) { w[NG][s_.value] *= cf.sigma2; });
 
+    VEC_MARK("sums");
+    VEC_TMARK(9);
     // ---------------- per-neighbourhood sums ----------------
     double part[NPART];
     sfor<0, NPART>([&](auto e_) { part[e_.value] = 0.0; });
@@ -499,6 +610,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     });
     sfor<0, NPART>([&](auto e_) { part[e_.value] = row_allreduce(part[e_.value]); });
 
+    VEC_MARK("accumulate");
+    VEC_TMARK(10);
     if (active && l == LS) {
       const double Lyq = rhs[0][SS];
       bool nonfinite = !(__builtin_isfinite(Lyq));
@@ -527,7 +640,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       };
       auto LXq = [&](auto t_) -> double { return rhs[1 + decltype(t_)::value][SS]; };
       double* ac = acc[grp];
-      ac[0] += log(vself);
+      int ex;
+      vprod[grp][0] = frexp(vprod[grp][0] * vself, &ex);
+      vprod[grp][1] += (double)ex;
       ac[1] += Lyq * Lyq;
       constexpr int oXSX = 2, oySX = oXSX + PC * PC, odl = oySX + PC, ody = odl + P,
                     odX = ody + P, odyX = odX + P * PC * PC, oin = odyX + P * PC;
@@ -556,11 +671,18 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         atomicMin(&status[1], (int32_t)i);
       }
     }
-    if (active && badnn) {
-      atomicOr(&status[0], 2);
+    VEC_TMARK(11);
+    if (active && (badnn || badval)) {
+      atomicOr(&status[0], (badnn ? 2 : 0) | (badval ? 4 : 0));
       atomicMin(&status[1], (int32_t)i);
     }
     __syncthreads();
+  }
+  VEC_TFLUSH;
+  __syncthreads();
+  if (threadIdx.x < kGroupsPerBlock) {
+    // logdet of the group: log of the running product of the v's
+    acc[threadIdx.x][0] = log(vprod[threadIdx.x][0]) + vprod[threadIdx.x][1] * 0.6931471805599453;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < NRAW; e += kThreads)
