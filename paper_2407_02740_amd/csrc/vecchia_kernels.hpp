@@ -56,6 +56,8 @@
 
 namespace vecchia {
 
+#include "exp_table.inc"
+
 #ifdef VECCHIA_ISA_MARKS
 #define VEC_MARK(x) asm volatile(";@@ " x)
 #else
@@ -135,6 +137,13 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
   return __builtin_fma(y0 * e, __builtin_fma(0.375, e, 0.5), y0);
 }
 
+// 1/x for x > 0: hardware estimate refined to y0 (1 + e + e^2), e = 1 - x y0.
+__device__ __forceinline__ double rcp_refined(double x) {
+  const double y0 = __builtin_amdgcn_rcp(x);
+  const double e = __builtin_fma(-x, y0, 1.0);
+  return __builtin_fma(y0, __builtin_fma(e, e, e), y0);
+}
+
 template <int K>
 struct Geo {
   static constexpr int NS = (K + 15) / 16;
@@ -151,6 +160,12 @@ struct Geo {
     return ((r / 16) & 1) ? 16 * (r / 16) + 15 - r : r - 16 * (r / 16);
   }
 };
+
+// LDS ordering between the lanes of one wavefront.  A workgroup is a single
+// wave64 and LDS instructions of a wave complete in issue order, so a
+// wavefront-scope fence (compiler ordering, no wait) is all that cross-lane
+// communication through LDS needs.
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 __device__ __forceinline__ int row_of(int s, int l) { return 16 * s + ((s & 1) ? 15 - l : l); }
 
@@ -216,19 +231,18 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   constexpr int NR = NG + 1;  // parameters whose w has entries above the self row
   constexpr int NRAW = nraw_of(PC, P);
   constexpr int LPN = K * (K - 1) / 2;  // strictly lower L, index r(r-1)/2 + c
+  static_assert(K % 16 != 0, "rows >= K serve as spare rows");
   constexpr int SS = G::slot_of(K - 1);
   constexpr int LS = G::lane_of(K - 1);
   constexpr int NGR = NR * (NR + 1) / 2;
   constexpr int NPART = NR + NR * PC + NGR;
 
   // per-row record: scaled coordinates z[0..3] (space-time: time in z[3])
-  // and u; the products g_rho = dSigma/drho u live in their own array so
-  // that reads of rec never wait behind the ds_add_f64 into g
+  // and u
   constexpr int RZ = 0, RU = 4;
   constexpr int RS = 6;  // row stride, 16-byte aligned
   __shared__ double rec[kGroupsPerBlock][KP][RS];
-  __shared__ double gvec[kGroupsPerBlock][KP][NG];
-  __shared__ double Lp[kGroupsPerBlock][LPN];
+  __shared__ double Lp[kGroupsPerBlock][LPN + 16];  // + one write sink per lane
   __shared__ double acc[kGroupsPerBlock][NRAW];
   // running product of conditional variances (mantissa, exponent)
   __shared__ double vprod[kGroupsPerBlock][2];
@@ -236,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   // from which every range derivative of the pair follows (last slot: sink
   // for diagonal entries)
   constexpr int NPAIR = KP * (KP - 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][NPAIR + 1];
+  __shared__ double sfv[kGroupsPerBlock][NPAIR + 2];  // + write sink, + zero
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -256,6 +270,11 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   const double inv_sigma2 = 1.0 / cf.sigma2;
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
+  if (threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
+  __shared__ double exptab[64];
+  static_assert(kThreads == 64, "one table entry per thread");
+  exptab[threadIdx.x] = kExp2Tab[threadIdx.x];
+  __syncthreads();
   if (threadIdx.x < kGroupsPerBlock) {
     vprod[threadIdx.x][0] = 1.0;
     vprod[threadIdx.x][1] = 0.0;
@@ -263,17 +282,68 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
 
   VEC_TDECL
   const int64_t total = i1 - i0;
-  for (int64_t base = (int64_t)blockIdx.x * kGroupsPerBlock; base < total;
-       base += (int64_t)gridDim.x * kGroupsPerBlock) {
+  const int64_t stride = (int64_t)gridDim.x * kGroupsPerBlock;
+
+  // Neighbour indices of observation ii for this lane's rows: id = -1 for
+  // padding rows (and rows >= K), ii for the self row.  Only valid columns
+  // 1..q of the NNarray row are read (column 0 otherwise).
+  auto fetch_ids = [&](int64_t ii, int lan, int64_t(&id)[NS], bool& bad) {
+    const int qq = (int)(ii < (int64_t)m ? ii : (int64_t)m);
+    const int32_t* row = NN + ii * (int64_t)(m + 1);
+    bad = (row[0] != (int32_t)ii);
+    sfor<0, NS>([&](auto s_) {
+      constexpr int s = s_.value;
+      const int r = row_of(s, lan);
+      const bool nb = r < qq;
+      const int64_t j = row[nb ? 1 + r : 0];
+      const bool okj = (j >= 0) && (j < ii);
+      bad = bad || (nb && !okj);
+      id[s] = (r == K - 1) ? ii : ((nb && okj) ? j : (int64_t)-1);
+    });
+  };
+  // Raw coordinates, y and X of those rows (row ii stands in for padding).
+  auto fetch_vals = [&](int64_t ii, const int64_t(&id)[NS], double(&zv)[NS][4],
+                        double(&yv)[NS], double(&xv)[NS][PC]) {
+    sfor<0, NS>([&](auto s_) {
+      constexpr int s = s_.value;
+      const int64_t ids = (id[s] >= 0) ? id[s] : ii;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) zv[s][k] = (k < d) ? locs[ids * d + k] : 0.0;
+      yv[s] = y[ids];
+#pragma unroll
+      for (int t = 0; t < PC; ++t) xv[s][t] = X[ids * PC + t];
+    });
+  };
+  auto obs_of = [&](int64_t bse) -> int64_t {
+    return i0 + ((bse + grp < total) ? bse + grp : total - 1);
+  };
+
+  // Software pipeline over the wave's neighbourhoods: the next NNarray row
+  // is loaded at the top of an iteration and the next coordinates, y and X
+  // after phase 1, so each gather finds its inputs in registers.
+  int64_t idc[NS];
+  bool badc = false;
+  double zv[NS][4], yv[NS], xv[NS][PC];
+  if ((int64_t)blockIdx.x * kGroupsPerBlock < total) {
+    const int64_t ii = obs_of((int64_t)blockIdx.x * kGroupsPerBlock);
+    fetch_ids(ii, lane, idc, badc);
+    fetch_vals(ii, idc, zv, yv, xv);
+  }
+
+  for (int64_t base = (int64_t)blockIdx.x * kGroupsPerBlock; base < total; base += stride) {
     // an opaque copy of the lane id per iteration keeps the many
     // lane-dependent predicates from being hoisted out of the loop
     int l = lane;
     asm volatile("" : "+v"(l));
     const bool active = base + grp < total;
-    const int64_t i = i0 + (active ? base + grp : total - 1);
+    const int64_t i = obs_of(base);
     const int q = (int)(i < (int64_t)m ? i : (int64_t)m);
-    const int32_t* nnrow = NN + i * (int64_t)(m + 1);
-    bool badnn = false;
+    const bool more = base + stride < total;
+    const int64_t inext = more ? obs_of(base + stride) : i;
+    int64_t idn[NS];
+    sfor<0, NS>([&](auto s_) { idn[s_.value] = -1; });
+    bool badn = false;
+    bool badnn = badc;
     bool badval = false;
 
     VEC_MARK("gather");
@@ -285,22 +355,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     // with no masking anywhere below.
     double zo[NS][4];
     double rhs[1 + PC][NS];
-    if (l == LS) badnn |= (nnrow[0] != (int32_t)i);
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
-      int64_t id = -1;
-      if (r == K - 1) {
-        id = i;
-      } else if (r < q) {
-        const int64_t j = nnrow[1 + r];
-        if (j < 0 || j >= i)
-          badnn = true;
-        else
-          id = j;
-      }
-      const bool has = id >= 0;
-      const int64_t ids = has ? id : i;  // always a valid row for the loads
+      const bool has = idc[s] >= 0;
       // isotropic: coordinate k in z[k]; space-time: spatial coordinates
       // 0..d-2 in z[0..d-2] scaled by 1/rho_s, time (coordinate d-1) in z[3]
       // scaled by 1/rho_t
@@ -308,8 +366,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (k < d) {
-          const double v = locs[ids * d + k];
-          badval |= !__builtin_isfinite(v);
+          const double v = zv[s][k];
+          badval |= has && !__builtin_isfinite(v);
           if (NG == 2 && k == d - 1)
             zc[3] = v * cf.ir[1];
           else
@@ -321,27 +379,58 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         zo[s][k] = has ? zc[k] : ((k == 0) ? kFar * (double)(1 + r) : 0.0);
         rec[grp][r][RZ + k] = zo[s][k];
       }
-      rhs[0][s] = has ? y[ids] : 0.0;
+      rhs[0][s] = has ? yv[s] : 0.0;
 #pragma unroll
-      for (int t = 0; t < PC; ++t) rhs[1 + t][s] = has ? X[ids * PC + t] : 0.0;
+      for (int t = 0; t < PC; ++t) rhs[1 + t][s] = has ? xv[s][t] : 0.0;
     });
-    __syncthreads();
+    // next NNarray row, in flight during phase 1
+    if (more) fetch_ids(inext, l, idn, badn);
+    wave_lds_fence();
 
-    // covariance of two distinct scaled locations, and the pair's range
-    // derivative factor sigma2 (-f'(h)/h) stored at sfv[idx]
-    auto pair_eval = [&](const double* za, const double* zb, int idx) -> double {
-      double h2 = 0.0;
+    // Covariance of two pairs of scaled locations (evaluated side by side so
+    // that their latencies overlap), and each pair's range-derivative factor
+    // sigma2 (-f'(h)/h) stored at sfv[idx].  exp(-h) is table driven: with
+    // -h = (64 m + j) ln2/64 + r, |r| <= ln2/128,
+    //   e^-h = 2^m * T[j] * (1 + q),  T[j] = 2^(j/64),
+    //   q = r + r^2/2 + ... + r^5/120 (truncation below 4e-17 relative),
+    // formed as T + T q; -h is clamped at -800 so that 2^m underflows to 0.
+    auto pair_eval2 = [&](const double* za0, const double* zb0, int idx0, const double* za1,
+                          const double* zb1, int idx1, double& v0, double& v1) {
+      double h20 = 0.0, h21 = 0.0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double t = za[k] - zb[k];
-        h2 = __builtin_fma(t, t, h2);
+        const double t0 = za0[k] - zb0[k];
+        const double t1 = za1[k] - zb1[k];
+        h20 = __builtin_fma(t0, t0, h20);
+        h21 = __builtin_fma(t1, t1, h21);
       }
-      double h, hinv;
-      dist_from_sq(h2, h, hinv);
-      const double sE = cf.sigma2 * exp_neg(h);
-      const double sF = sE * __builtin_fma(cf.a1, h, __builtin_fma(cf.a2, hinv, cf.a0));
-      sfv[grp][idx] = (NG == 1) ? sF * h2 * cf.ir[0] : sF;
-      return sE * __builtin_fma(h, __builtin_fma(h, cf.c2, cf.c1), 1.0);
+      double hh0, hi0, hh1, hi1;
+      dist_from_sq(h20, hh0, hi0);
+      dist_from_sq(h21, hh1, hi1);
+      const double x0 = fmax(-hh0, -800.0), x1 = fmax(-hh1, -800.0);
+      const double n0 = rint(x0 * kInvLn2x64), n1 = rint(x1 * kInvLn2x64);
+      const int i0n = (int)n0, i1n = (int)n1;
+      const double T0 = exptab[i0n & 63], T1 = exptab[i1n & 63];
+      double r0 = __builtin_fma(-n0, kLn2d64Hi, x0), r1 = __builtin_fma(-n1, kLn2d64Hi, x1);
+      r0 = __builtin_fma(-n0, kLn2d64Lo, r0);
+      r1 = __builtin_fma(-n1, kLn2d64Lo, r1);
+      double q0 = __builtin_fma(r0, 1.0 / 120.0, 1.0 / 24.0), q1 = __builtin_fma(r1, 1.0 / 120.0, 1.0 / 24.0);
+      q0 = __builtin_fma(q0, r0, 1.0 / 6.0);
+      q1 = __builtin_fma(q1, r1, 1.0 / 6.0);
+      q0 = __builtin_fma(q0, r0, 0.5);
+      q1 = __builtin_fma(q1, r1, 0.5);
+      q0 = __builtin_fma(q0, r0, 1.0);
+      q1 = __builtin_fma(q1, r1, 1.0);
+      q0 *= r0;
+      q1 *= r1;
+      const double sE0 = cf.sigma2 * ldexp(__builtin_fma(T0, q0, T0), i0n >> 6);
+      const double sE1 = cf.sigma2 * ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
+      const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
+      const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
+      sfv[grp][idx0] = (NG == 1) ? sF0 * h20 * cf.ir[0] : sF0;
+      sfv[grp][idx1] = (NG == 1) ? sF1 * h21 * cf.ir[0] : sF1;
+      v0 = sE0 * __builtin_fma(hh0, __builtin_fma(hh0, cf.c2, cf.c1), 1.0);
+      v1 = sE1 * __builtin_fma(hh1, __builtin_fma(hh1, cf.c2, cf.c1), 1.0);
     };
     auto pidx = [](int r, int c) { return r * (r - 1) / 2 + c; };
 
@@ -352,39 +441,91 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     // step may write its value into both candidate registers.
     double A[NL];
     sfor<0, NL>([&](auto e_) { A[e_.value] = 0.0; });
-    // off-diagonal 16x16 blocks: slot s rows x columns of block t < s
+    // off-diagonal 16x16 blocks: slot s rows x columns of block t < s, two
+    // columns per step, partner coordinates read one step ahead
     sfor<1, NS>([&](auto s_) {
       constexpr int s = s_.value;
       sfor<0, s>([&](auto t_) {
         constexpr int t = t_.value;
-        sfor<0, 16>([&](auto cc_) {
-          constexpr int c = 16 * t + cc_.value;
-          double zc[4];
+        double zn[2][4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
-          A[G::off(s) + c] = pair_eval(zo[s], zc, pidx(row_of(s, l), c));
+        for (int k = 0; k < 4; ++k) {
+          zn[0][k] = rec[grp][16 * t][RZ + k];
+          zn[1][k] = rec[grp][16 * t + 1][RZ + k];
+        }
+        sfor<0, 8>([&](auto cc_) {
+          constexpr int c = 16 * t + 2 * cc_.value;
+          double zc[2][4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            zc[0][k] = zn[0][k];
+            zc[1][k] = zn[1][k];
+          }
+          if constexpr (cc_.value + 1 < 8) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              zn[0][k] = rec[grp][c + 2][RZ + k];
+              zn[1][k] = rec[grp][c + 3][RZ + k];
+            }
+          }
+          const int r = row_of(s, l);
+          pair_eval2(zo[s], zc[0], pidx(r, c), zo[s], zc[1], pidx(r, c + 1), A[G::off(s) + c],
+                     A[G::off(s) + c + 1]);
         });
       });
     });
-    // diagonal blocks of slots (2t, 2t+1) folded into 17 steps
+    // diagonal blocks of slots (2t, 2t+1) folded into 17 steps (two per
+    // evaluation): lane l takes row 16 s0 + l's entry at column 16 s0 + u
+    // while u <= l, else row 16 s1 + 15 - l's entry at column 16 s1 + 16 - u
     sfor<0, NS / 2>([&](auto t_) {
       constexpr int s0 = 2 * t_.value;
       constexpr int s1 = s0 + 1;
-      sfor<0, 17>([&](auto u_) {
-        constexpr int u = u_.value;
+      auto locate = [&](auto u_, int& r, int& c, double(&zr)[4], double(&zc)[4]) {
+        constexpr int u = decltype(u_)::value;
         const bool first = (u <= l);
-        const int c = first ? 16 * s0 + u : 16 * s1 + 16 - u;
-        const int r = first ? 16 * s0 + l : 16 * s1 + 15 - l;
-        double zr[4], zc[4];
+        c = first ? 16 * s0 + u : 16 * s1 + 16 - u;
+        r = first ? 16 * s0 + l : 16 * s1 + 15 - l;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           zr[k] = rec[grp][r][RZ + k];
           zc[k] = rec[grp][c][RZ + k];
         }
-        const double off = pair_eval(zr, zc, (c == r) ? NPAIR : pidx(r, c));
+      };
+      auto store = [&](auto u_, int r, int c, double off) {
+        constexpr int u = decltype(u_)::value;
         const double v = (c == r) ? cf.diag : off;
         if constexpr (u <= 15) A[G::off(s0) + 16 * s0 + u] = v;
         if constexpr (u >= 1 && 16 * s1 + 16 - u < K) A[G::off(s1) + 16 * s1 + 16 - u] = v;
+      };
+      int rn[2], cn[2];
+      double zrn[2][4], zcn[2][4];
+      locate(std::integral_constant<int, 0>{}, rn[0], cn[0], zrn[0], zcn[0]);
+      locate(std::integral_constant<int, 1>{}, rn[1], cn[1], zrn[1], zcn[1]);
+      sfor<0, 9>([&](auto w_) {
+        constexpr int u = 2 * w_.value;          // steps u and u + 1 (17 steps)
+        int r[2] = {rn[0], rn[1]}, c[2] = {cn[0], cn[1]};
+        double zr[2][4], zc[2][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          zr[0][k] = zrn[0][k];
+          zc[0][k] = zcn[0][k];
+          zr[1][k] = zrn[1][k];
+          zc[1][k] = zcn[1][k];
+        }
+        if constexpr (u + 2 < 17) locate(std::integral_constant<int, u + 2>{}, rn[0], cn[0], zrn[0], zcn[0]);
+        if constexpr (u + 3 < 17) locate(std::integral_constant<int, u + 3>{}, rn[1], cn[1], zrn[1], zcn[1]);
+        double off0, off1;
+        if constexpr (u + 1 < 17) {
+          pair_eval2(zr[0], zc[0], (c[0] == r[0]) ? NPAIR : pidx(r[0], c[0]), zr[1], zc[1],
+                     (c[1] == r[1]) ? NPAIR : pidx(r[1], c[1]), off0, off1);
+          store(std::integral_constant<int, u>{}, r[0], c[0], off0);
+          store(std::integral_constant<int, u + 1>{}, r[1], c[1], off1);
+        } else {
+          // last (odd) step: the second slot of the evaluation repeats it
+          pair_eval2(zr[0], zc[0], (c[0] == r[0]) ? NPAIR : pidx(r[0], c[0]), zr[0], zc[0],
+                     NPAIR, off0, off1);
+          store(std::integral_constant<int, u>{}, r[0], c[0], off0);
+        }
       });
     });
     // unpaired last slot (odd NS): its triangle directly
@@ -396,16 +537,19 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         double zc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
-        const double off = pair_eval(zo[s], zc, (c < r) ? pidx(r, c) : NPAIR);
+        double off, dup;
+        pair_eval2(zo[s], zc, (c < r) ? pidx(r, c) : NPAIR, zo[s], zc, NPAIR, off, dup);
         A[G::off(s) + c] = (c == r) ? cf.diag : off;
       });
     }
 
     VEC_MARK("cholesky");
     VEC_TMARK(3);
-    // ---------------- Cholesky (right-looking, in registers) ----------------
-    // Scaling column c by 1/sqrt(pivot) turns the pivot entry itself into
-    // sqrt(pivot); only the owner of row c keeps 1/L_cc (idg).
+    // ---------------- LDL^T factorisation (right-looking, in registers) ----------------
+    // Sigma = Lt D Lt^T with Lt unit lower triangular, so L = Lt D^(1/2) and
+    // every substitution below runs on Lt without divisions.  Column c:
+    // broadcast the pivot d_c and each unscaled entry A[r][c]; rows update
+    // with Lt[row][c] = A[row][c] / d_c.  The owner of row r keeps 1/d_r.
     double idg[NS];
     sfor<0, NS>([&](auto s_) { idg[s_.value] = 0.0; });
     bool notpd = false;
@@ -416,28 +560,33 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       constexpr int lc = G::lane_of(c);
       const double dv = bcast<lc>(A[G::off(sc) + c]);
       notpd |= !(dv > 0.0);
-      const double rs = rsqrt_refined(dv);
+      const double ri = rcp_refined(dv);
       if constexpr (c == K - 1) vself = dv;
+      idg[sc] = (row_of(sc, l) == c) ? ri : idg[sc];
+      double Ls[NS];
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (16 * s + 15 >= c) A[G::off(s) + c] *= rs;
+        if constexpr (16 * s + 15 > c) Ls[s] = A[G::off(s) + c] * ri;
       });
-      idg[sc] = (row_of(sc, l) == c) ? rs : idg[sc];
       sfor<c + 1, K>([&](auto r_) {
         constexpr int r = r_.value;
         constexpr int sr = r / 16;
         constexpr int lr = G::lane_of(r);
-        const double lrc = bcast<lr>(A[G::off(sr) + c]);
+        const double arc = bcast<lr>(A[G::off(sr) + c]);
         sfor<0, NS>([&](auto s_) {
           constexpr int s = s_.value;
           if constexpr (16 * s + 15 >= r)
-            A[G::off(s) + r] = __builtin_fma(-A[G::off(s) + c], lrc, A[G::off(s) + r]);
+            A[G::off(s) + r] = __builtin_fma(-Ls[s], arc, A[G::off(s) + r]);
         });
+      });
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        if constexpr (16 * s + 15 > c) A[G::off(s) + c] = Ls[s];
       });
     });
     VEC_MARK("zero_upper");
     VEC_TMARK(4);
-    // keep only the strict lower triangle (diagonal lives in idg as 1/L_rr)
+    // keep only the strict lower triangle of Lt (unit diagonal implied)
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
@@ -447,136 +596,169 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       });
     });
 
-    // forward substitution x <- L^{-1} x for NV right-hand sides
-    auto fwd = [&](auto& x) {
+    // forward substitution x <- Lt^{-1} x (unit lower) for NV right-hand
+    // sides, one column step at a time
+    auto fwd_step = [&](auto c_, auto& x) {
+      constexpr int c = decltype(c_)::value;
       constexpr int NV = std::extent<std::remove_reference_t<decltype(x)>, 0>::value;
-      sfor<0, K>([&](auto c_) {
-        constexpr int c = c_.value;
-        constexpr int sc = c / 16;
-        constexpr int lc = G::lane_of(c);
-        sfor<0, NV>([&](auto v_) {
-          constexpr int v = v_.value;
-          const double xc = bcast<lc>(x[v][sc] * idg[sc]);
-          sfor<0, NS>([&](auto s_) {
-            constexpr int s = s_.value;
-            if constexpr (16 * s + 15 > c)
-              x[v][s] = __builtin_fma(-A[G::off(s) + c], xc, x[v][s]);
-          });
+      constexpr int sc = c / 16;
+      constexpr int lc = G::lane_of(c);
+      sfor<0, NV>([&](auto v_) {
+        constexpr int v = v_.value;
+        const double xc = bcast<lc>(x[v][sc]);
+        sfor<0, NS>([&](auto s_) {
+          constexpr int s = s_.value;
+          if constexpr (16 * s + 15 > c) x[v][s] = __builtin_fma(-A[G::off(s) + c], xc, x[v][s]);
         });
       });
-      sfor<0, NV>([&](auto v_) {
-        sfor<0, NS>([&](auto s_) { x[v_.value][s_.value] *= idg[s_.value]; });
-      });
     };
-    VEC_MARK("fwd_rhs");
-    VEC_TMARK(5);
-    fwd(rhs);  // Liy, LiX
+    auto fwd = [&](auto& x) { sfor<0, K>([&](auto c_) { fwd_step(c_, x); }); };
 
+    // ---------------- ut = Lt^{-T} e_last via Lt in LDS ----------------
     VEC_MARK("backsolve");
     VEC_TMARK(6);
-    // ---------------- u = L^{-T} e_last via L in LDS ----------------
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
       sfor<0, G::len(s)>([&](auto c_) {
         constexpr int c = c_.value;
-        if (c < r && r < K) Lp[grp][r * (r - 1) / 2 + c] = A[G::off(s) + c];
+        Lp[grp][(c < r && r < K) ? r * (r - 1) / 2 + c : LPN + l] = A[G::off(s) + c];
       });
     });
     double uu[NS];
     sfor<0, NS>([&](auto s_) { uu[s_.value] = (row_of(s_.value, l) == K - 1) ? 1.0 : 0.0; });
-    __syncthreads();
-    sfor<0, K>([&](auto cc_) {
-      constexpr int r = K - 1 - cc_.value;
-      constexpr int sr = r / 16;
-      constexpr int lr = G::lane_of(r);
-      const double ur = bcast<lr>(uu[sr] * idg[sr]);
+    wave_lds_fence();
+    // Lt[r][row] for step r (0 where row >= r), read PF steps ahead
+    auto lrow = [&](auto r_, double(&lv)[NS]) {
+      constexpr int r = decltype(r_)::value;
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (16 * s < r) {
+        if constexpr (r > 0 && 16 * s < r) {
           const int row = row_of(s, l);
-          if constexpr (16 * s + 15 < r) {
-            uu[s] = __builtin_fma(-Lp[grp][r * (r - 1) / 2 + row], ur, uu[s]);
-          } else {
-            const double lv = Lp[grp][r * (r - 1) / 2 + (row < r ? row : r - 1)];
-            uu[s] = (row < r) ? __builtin_fma(-lv, ur, uu[s]) : uu[s];
-          }
+          const double v = Lp[grp][r * (r - 1) / 2 + (row < r ? row : r - 1)];
+          lv[s] = (row < r) ? v : 0.0;
+        } else {
+          lv[s] = 0.0;
         }
       });
+    };
+    constexpr int PF = (K < 3) ? K : 3;
+    double lvq[PF][NS];
+    sfor<0, PF>([&](auto x_) { lrow(std::integral_constant<int, K - 1 - x_.value>{}, lvq[x_.value]); });
+    // The back substitution (latency bound: one broadcast per step) runs
+    // interleaved with the independent forward substitution of y and X.
+    sfor<0, K>([&](auto x_) {
+      constexpr int x = x_.value;
+      constexpr int r = K - 1 - x;
+      constexpr int sr = r / 16;
+      constexpr int lr = G::lane_of(r);
+      double lv[NS];
+      sfor<0, NS>([&](auto s_) { lv[s_.value] = lvq[x % PF][s_.value]; });
+      if constexpr (r - PF >= 0) lrow(std::integral_constant<int, r - PF>{}, lvq[x % PF]);
+      const double ur = bcast<lr>(uu[sr]);
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        if constexpr (16 * s < r) uu[s] = __builtin_fma(-lv[s], ur, uu[s]);
+      });
+      fwd_step(x_, rhs);
     });
+    // rhs = Lt^{-1} (y, X);  uu = Lt^{-T} e_last (u = uu / sqrt(d_last))
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
-      uu[s] *= idg[s];
-      const int r = row_of(s, l);
-      if (r < K) {
-        rec[grp][r][RU] = uu[s];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) gvec[grp][r][g] = 0.0;
-      }
+      rec[grp][row_of(s, l)][RU] = uu[s];  // 0 for rows >= K
     });
-    __syncthreads();
+    wave_lds_fence();
 
+    if (more) fetch_vals(inext, idn, zv, yv, xv);  // next neighbourhood, in flight until the next gather
     VEC_MARK("phase2");
     VEC_TMARK(7);
-    // ---------------- phase 2: g_rho = dSigma/drho * u (tournament) ----------------
+    // ---------------- phase 2: g_rho = dSigma/drho * u (row layout) ----------------
+    // g[a] = sum_b D_ab u_b for this lane's rows a: the pair factor comes
+    // from sfv (static offsets off the diagonal block, the zero slot on the
+    // diagonal), u_b and z_b are uniform reads, one column ahead of use.
     // Pairs with a padding row have exp(-h) = 0 and add nothing.
-    {
-      constexpr int KO = (K & 1) ? K : K + 1;
-      constexpr int M2 = (KO - 1) / 2;
-      constexpr int NSUB = (M2 + 15) / 16;
-      sfor<0, KO>([&](auto t_) {
-        constexpr int t = t_.value;
-        sfor<0, NSUB>([&](auto j_) {
-          const int sidx = 1 + l + 16 * j_.value;
-          int a = t + sidx;
-          a -= (a >= KO) ? KO : 0;
-          int b = t - sidx;
-          b += (b < 0) ? KO : 0;
-          if (sidx <= M2 && (KO == K || (a < K && b < K))) {
-            const int hi = a > b ? a : b, lo = a > b ? b : a;
-            const double sF = sfv[grp][pidx(hi, lo)];
-            const double* ra = rec[grp][a];
-            const double* rb = rec[grp][b];
-            double* ga = gvec[grp][a];
-            double* gb = gvec[grp][b];
-            const double ua = ra[RU], ub = rb[RU];
-            if constexpr (NG == 1) {
-              // stored directly as dSigma/drho for the isotropic family
-              atomicAdd(&ga[0], sF * ub);
-              atomicAdd(&gb[0], sF * ua);
-            } else {
-              double h2s = 0.0;
+    double gr[NG][NS];
+    int base_a[NS];
+    double zrow[NS][4];
+    sfor<0, NS>([&](auto s_) {
+      constexpr int s = s_.value;
+      const int a = row_of(s, l);
+      base_a[s] = a * (a - 1) / 2;
+      if constexpr (NG == 2) {
 #pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                const double dz = ra[RZ + k] - rb[RZ + k];
-                h2s = __builtin_fma(dz, dz, h2s);
-              }
-              const double dt = ra[RZ + 3] - rb[RZ + 3];
-              const double D0 = sF * h2s * cf.ir[0];
-              const double D1 = sF * (dt * dt) * cf.ir[1];
-              atomicAdd(&ga[0], D0 * ub);
-              atomicAdd(&gb[0], D0 * ua);
-              atomicAdd(&ga[1], D1 * ub);
-              atomicAdd(&gb[1], D1 * ua);
+        for (int k = 0; k < 4; ++k) zrow[s][k] = rec[grp][a][RZ + k];
+      }
+#pragma unroll
+      for (int g = 0; g < NG; ++g) gr[g][s] = 0.0;
+    });
+    auto col_load = [&](auto b_, double& ub, double(&zb)[4], double(&Sv)[NS]) {
+      constexpr int b = decltype(b_)::value;
+      constexpr int CB = b * (b - 1) / 2;
+      ub = rec[grp][b][RU];
+      if constexpr (NG == 2) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zb[k] = rec[grp][b][RZ + k];
+      }
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        const int a = row_of(s, l);
+        int idx;
+        if constexpr (b < 16 * s)
+          idx = base_a[s] + b;
+        else if constexpr (b >= 16 * (s + 1))
+          idx = a + CB;
+        else
+          idx = (b < a) ? base_a[s] + b : ((b > a) ? a + CB : NPAIR + 1);
+        Sv[s] = sfv[grp][idx];
+      });
+    };
+    {
+      double ubn, zbn[4], Svn[NS];
+      col_load(std::integral_constant<int, 0>{}, ubn, zbn, Svn);
+      sfor<0, K>([&](auto b_) {
+        constexpr int b = b_.value;
+        double ub = ubn, zb[4], Sv[NS];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zb[k] = zbn[k];
+        sfor<0, NS>([&](auto s_) { Sv[s_.value] = Svn[s_.value]; });
+        if constexpr (b + 1 < K) col_load(std::integral_constant<int, b + 1>{}, ubn, zbn, Svn);
+        sfor<0, NS>([&](auto s_) {
+          constexpr int s = s_.value;
+          if constexpr (NG == 1) {
+            // stored directly as dSigma/drho for the isotropic family
+            gr[0][s] = __builtin_fma(Sv[s], ub, gr[0][s]);
+          } else {
+            double h2s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              const double dz = zrow[s][k] - zb[k];
+              h2s = __builtin_fma(dz, dz, h2s);
             }
+            const double dt = zrow[s][3] - zb[3];
+            const double Su = Sv[s] * ub;
+            gr[0][s] = __builtin_fma(Su, h2s, gr[0][s]);
+            gr[1][s] = __builtin_fma(Su, dt * dt, gr[1][s]);
           }
         });
       });
     }
-    __syncthreads();
+    if constexpr (NG == 2) {
+      sfor<0, NS>([&](auto s_) {
+        gr[0][s_.value] *= cf.ir[0];
+        gr[1][s_.value] *= cf.ir[1];
+      });
+    }
 
     VEC_MARK("w_solve");
     VEC_TMARK(8);
     // ---------------- w = L^{-1} (dSigma_j u) ----------------
-    // range parameters: g_rho from phase 2; tau2: dSigma = sigma2 I, so
-    // w_tau2 = sigma2 L^{-1} u (one more forward solve)
+    // range parameters: g_rho from phase 2; tau2: dSigma = sigma2 I.  In the
+    // Lt form wt_j = Lt^{-1} dSigma_j uu, and w_j[l] = wt_j[l] / sqrt(d_l d_q).
     double w[NR][NS];
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
-      const int r = row_of(s, l);
-      const int rc = r < K ? r : K - 1;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) w[g][s] = (r < K) ? gvec[grp][rc][g] : 0.0;
+      for (int g = 0; g < NG; ++g) w[g][s] = gr[g][s];
       w[NG][s] = uu[s];
     });
     fwd(w);
@@ -585,18 +767,22 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     VEC_MARK("sums");
     VEC_TMARK(9);
     // ---------------- per-neighbourhood sums ----------------
+    // Sums over rows l < q in the Lt form: Sy_j = sum wt_j yt / d_l (times
+    // 1/sqrt(d_q) later), SX_j likewise, G_jk = sum wt_j wt_k / d_l (times 1/d_q).
     double part[NPART];
     sfor<0, NPART>([&](auto e_) { part[e_.value] = 0.0; });
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
-      const double keep = (row_of(s, l) < K - 1) ? 1.0 : 0.0;
+      const double keep = (row_of(s, l) < K - 1) ? idg[s] : 0.0;
+      double ws[NR];
+      sfor<0, NR>([&](auto j_) { ws[j_.value] = keep * w[j_.value][s]; });
       sfor<0, NR>([&](auto j_) {
-        part[j_.value] = __builtin_fma(keep * w[j_.value][s], rhs[0][s], part[j_.value]);
+        part[j_.value] = __builtin_fma(ws[j_.value], rhs[0][s], part[j_.value]);
       });
       sfor<0, NR>([&](auto j_) {
         sfor<0, PC>([&](auto t_) {
           constexpr int e = NR + j_.value * PC + t_.value;
-          part[e] = __builtin_fma(keep * w[j_.value][s], rhs[1 + t_.value][s], part[e]);
+          part[e] = __builtin_fma(ws[j_.value], rhs[1 + t_.value][s], part[e]);
         });
       });
       sfor<0, NR>([&](auto j_) {
@@ -604,7 +790,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         sfor<j, NR>([&](auto k_) {
           constexpr int k = k_.value;
           constexpr int e = NR + NR * PC + (j * (2 * NR - j + 1)) / 2 + (k - j);
-          part[e] = __builtin_fma(keep * w[j][s], w[k][s], part[e]);
+          part[e] = __builtin_fma(ws[j], w[k][s], part[e]);
         });
       });
     });
@@ -613,21 +799,26 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     VEC_MARK("accumulate");
     VEC_TMARK(10);
     if (active && l == LS) {
-      const double Lyq = rhs[0][SS];
+      // back from the Lt form to the quantities of the Cholesky factor L:
+      // Liy_q = yt_q / sqrt(d_q), w_j[q] = wt_j[q] / d_q, Sy_j, SX_j carry
+      // 1/sqrt(d_q), G_jk carries 1/d_q
+      const double iq = idg[SS];
+      const double sq = rsqrt_refined(vself);
+      const double Lyq = rhs[0][SS] * sq;
       bool nonfinite = !(__builtin_isfinite(Lyq));
       sfor<0, PC>([&](auto t_) { nonfinite |= !(__builtin_isfinite(rhs[1 + t_.value][SS])); });
       // parameter j: 0 -> sigma2 (w = e_last / sigma2), j >= 1 -> w[j - 1]
       auto wq = [&](auto j_) -> double {
         constexpr int j = decltype(j_)::value;
-        if constexpr (j == 0) return inv_sigma2; else return w[j - 1][SS];
+        if constexpr (j == 0) return inv_sigma2; else return w[j - 1][SS] * iq;
       };
       auto Sy = [&](auto j_) -> double {
         constexpr int j = decltype(j_)::value;
-        if constexpr (j == 0) return 0.0; else return part[j - 1];
+        if constexpr (j == 0) return 0.0; else return part[j - 1] * sq;
       };
       auto SX = [&](auto j_, auto t_) -> double {
         constexpr int j = decltype(j_)::value, t = decltype(t_)::value;
-        if constexpr (j == 0) return 0.0; else return part[NR + (j - 1) * PC + t];
+        if constexpr (j == 0) return 0.0; else return part[NR + (j - 1) * PC + t] * sq;
       };
       auto Gjk = [&](auto j_, auto k_) -> double {
         constexpr int j = decltype(j_)::value, k = decltype(k_)::value;
@@ -635,10 +826,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
           return 0.0;
         } else {
           constexpr int a = (j < k ? j : k) - 1, b = (j < k ? k : j) - 1;
-          return part[NR + NR * PC + (a * (2 * NR - a + 1)) / 2 + (b - a)];
+          return part[NR + NR * PC + (a * (2 * NR - a + 1)) / 2 + (b - a)] * iq;
         }
       };
-      auto LXq = [&](auto t_) -> double { return rhs[1 + decltype(t_)::value][SS]; };
+      auto LXq = [&](auto t_) -> double { return rhs[1 + decltype(t_)::value][SS] * sq; };
       double* ac = acc[grp];
       int ex;
       vprod[grp][0] = frexp(vprod[grp][0] * vself, &ex);
@@ -676,7 +867,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       atomicOr(&status[0], (badnn ? 2 : 0) | (badval ? 4 : 0));
       atomicMin(&status[1], (int32_t)i);
     }
-    __syncthreads();
+    sfor<0, NS>([&](auto s_) { idc[s_.value] = idn[s_.value]; });
+    badc = badn;
+    wave_lds_fence();
   }
   VEC_TFLUSH;
   __syncthreads();
