@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=262_144)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 512 MiB device-to-device copy (a kernel of known traffic "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
@@ -123,6 +126,14 @@ def main():
     F = algorithmic_flops(m + 1, d, p, R)
     achieved = F * n / (kernel_ms * 1e-3) / 1e12
     log(f"fused kernel {kernel_ms:.4f} ms, {F} flop/nbhd -> {achieved:.2f} TFLOP/s")
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 2 x 536870912-byte device copies")
 
     cpu = None
     if not args.no_cpu:

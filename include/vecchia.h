@@ -133,7 +133,7 @@ int vec_combine(const vec_problem* pb, const double* raw, double* out, int32_t* 
                 void* stream);
 
 /* vec_raw_sums over all n observations followed by vec_combine. */
-int vec_loglik_grad_info(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+int vecchia_loglik_grad_info(const vec_problem* pb, const double* locs, const int32_t* NNarray,
                          const double* y, const double* X, const double* covparms, double* raw,
                          double* out, void* workspace, size_t workspace_bytes, int32_t* status,
                          void* stream);

@@ -66,8 +66,8 @@ def lib():
                                      _VP, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32), _VP, _VP]
         L.vec_combine.restype = ctypes.c_int
         L.vec_combine.argtypes = [pp, _VP, _VP, _VP, _VP]
-        L.vec_loglik_grad_info.restype = ctypes.c_int
-        L.vec_loglik_grad_info.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+        L.vecchia_loglik_grad_info.restype = ctypes.c_int
+        L.vecchia_loglik_grad_info.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                            ctypes.c_size_t, _VP, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
@@ -210,13 +210,13 @@ class Vecchia:
         cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
             self.covparms(covparms)
         ws = self.workspace()
-        _check(lib().vec_loglik_grad_info(
+        _check(lib().vecchia_loglik_grad_info(
             ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
             self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), self.raw.data_ptr(),
             self.out.data_ptr(), ws.data_ptr(), ws.numel() * 8, self.status.data_ptr(), _stream()),
-            "vec_loglik_grad_info")
+            "vecchia_loglik_grad_info")
         if check:
-            self.check_status("vec_loglik_grad_info")
+            self.check_status("vecchia_loglik_grad_info")
         return self.out
 
     def fisher_update(self, covparms: torch.Tensor, max_step: float = 1.0):

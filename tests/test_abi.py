@@ -21,7 +21,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(V.LIB_PATH), reason="libvecch
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(vec_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(vec(?:chia)?_\w+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported():
