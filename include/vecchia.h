@@ -138,6 +138,41 @@ int vecchia_loglik_grad_info(const vec_problem* pb, const double* locs, const in
                          double* out, void* workspace, size_t workspace_bytes, int32_t* status,
                          void* stream);
 
+/* The profile log-likelihood alone: the sums of Algorithm 1 (Section 3)
+ * without the derivative and information work, then the combine step.
+ * raw receives [logdet, ySy, XSX[p][p], ySX[p]] (the first 2 + p*p + p
+ * entries of the raw layout; raw[nraw] is large enough), out receives
+ * [loglik, betahat[p], betainfo[p][p]] (1 + p + p*p doubles).  workspace as
+ * for vec_raw_sums over [0, n). */
+int vec_loglik(const vec_problem* pb, const double* locs, const int32_t* NNarray, const double* y,
+               const double* X, const double* covparms, double* raw, double* out, void* workspace,
+               size_t workspace_bytes, int32_t* status, void* stream);
+
+/* Reverse-mode (adjoint) gradient of the log-likelihood with respect to
+ * covparms at a given mean vector betahat[p] (device), every
+ * neighbourhood's factor recomputed and no derivative matrix stored.  With
+ * r = y - X betahat, v the conditional variance of observation i given its
+ * neighbours and z its standardised conditional residual (the last row of
+ * the neighbourhood's Cholesky factor L, Algorithm 1), u = L^-T e_last and
+ * alpha = Sigma_i^-1 r_i, each neighbourhood contributes
+ *   d/dtheta_j [-1/2 (log v + z^2)] =
+ *     -1/2 [ (u' dS_j u)(1 + z^2) - 2 z (alpha' dS_j u) ]
+ * (dS_j = dSigma_i/dtheta_j, Section 3's derivative matrices).  At betahat =
+ * the GLS estimate this is the gradient of the profile log-likelihood
+ * (grad[] of vecchia_loglik_grad_info).
+ *   grad_out   device FP64 scalar multiplying the gradient (the incoming
+ *              gradient of a reverse-mode caller), or NULL for 1.
+ *   loglik     device FP64 scalar receiving -1/2 (n log 2pi + logdet +
+ *              r' Sigma^-1 r) at betahat under the Vecchia factorisation, or
+ *              NULL.
+ *   dcovparms  device FP64 [P] receiving grad_out * d loglik / d covparms.
+ * workspace holds at least vec_workspace_bytes(pb, 0, n) bytes. */
+int vec_loglik_adjoint(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                       const double* y, const double* X, const double* covparms,
+                       const double* betahat, const double* grad_out, double* loglik,
+                       double* dcovparms, void* workspace, size_t workspace_bytes,
+                       int32_t* status, void* stream);
+
 /* One Fisher-scoring step, Eq. (4), on phi = log(covparms):
  * g = covparms .* grad, I = diag(covparms) info diag(covparms),
  * step = I^-1 g scaled to length max_step if longer, covparms *= exp(step).
@@ -148,8 +183,9 @@ int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms
                       int32_t* status, double max_step, void* stream);
 
 /* `iters` Fisher-scoring iterations (evaluate, reduce, combine, update), all
- * on the device.  With use_graph != 0 one iteration is captured once as a
- * HIP graph and replayed; otherwise the kernels are launched directly.
+ * on the device.  With use_graph != 0 and a non-NULL stream one iteration
+ * is captured once as a HIP graph and replayed (capture needs a stream of
+ * its own); otherwise the kernels are launched directly.
  * covparms is updated in place, out[] holds the last evaluation (taken at
  * the parameters before the last update). */
 int vec_fisher_fit(const vec_problem* pb, const double* locs, const int32_t* NNarray,

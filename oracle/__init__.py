@@ -12,6 +12,9 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
   cov_matrix    pinned: Matern via the Bessel-K definition (scipy), and
                 finite differences for the parameter derivatives.
   combine       pinned through the dense exact GP and the AR(1) closed form.
+  at_beta       pinned: central finite differences in theta at a fixed beta
+                away from beta_hat, the dense reverse-mode expression of the
+                gradient, and agreement with combine at beta_hat.
   fisher_step   pinned: the Eq. (4) update is a fixed point at the MLE of the
                 AR(1) closed form (scipy optimiser).
 """
@@ -20,6 +23,7 @@ from .oracle import (  # noqa: F401
     FAMILY_ISO,
     FAMILY_SPACETIME,
     OracleError,
+    at_beta,
     build,
     combine,
     cov_matrix,

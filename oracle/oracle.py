@@ -10,6 +10,8 @@ written from the paper's statement of the method:
                     into the profile log-likelihood, its gradient and the Fisher
                     information, with the mean parameters profiled out
                     (generalised least squares, Section 2.1 / Section 3).
+* ``at_beta``    -- the same log-likelihood and theta-gradient at a given
+                    (not profiled) mean vector beta.
 * ``fisher_step``-- one Fisher-scoring update, Eq. (4), taken on the log scale
                     of the (positive) covariance parameters with a unit cap on
                     the step length.
@@ -198,6 +200,26 @@ def combine(raw, n: int, p: int, P: int) -> dict:
                 + beta @ r["dXSX"][j] @ beta) for j in range(P)])
     return dict(loglik=loglik, grad=grad, info=r["ainfo"].copy(), betahat=beta,
                 betainfo=r["XSX"].copy())
+
+
+def at_beta(raw, n: int, p: int, P: int, beta) -> dict:
+    """Log-likelihood and its theta-gradient at a fixed mean vector beta.
+
+    With r = y - X beta the quadratic form of Eq. (2) expands in the sums as
+    ySy - 2 beta^T ySX + beta^T XSX beta, and each of its theta-derivatives
+    in the derivative sums likewise:
+    loglik = -1/2 (n log 2 pi + logdet + ySy - 2 beta^T ySX + beta^T XSX beta),
+    grad_j = -1/2 (dlogdet_j + dySy_j - 2 beta^T dySX_j + beta^T dXSX_j beta).
+    At beta = beta_hat these equal the profile values of ``combine``.
+    """
+    r = unpack_raw(raw, p, P)
+    beta = np.asarray(beta, dtype=np.float64).reshape(p)
+    quad = r["ySy"] - 2.0 * beta @ r["ySX"] + beta @ r["XSX"] @ beta
+    loglik = -0.5 * (n * math.log(2.0 * math.pi) + r["logdet"] + quad)
+    grad = np.array([
+        -0.5 * (r["dlogdet"][j] + r["dySy"][j] - 2.0 * beta @ r["dySX"][j]
+                + beta @ r["dXSX"][j] @ beta) for j in range(P)])
+    return dict(loglik=loglik, grad=grad)
 
 
 def loglik_grad_info(locs, NN, y, X, covparms, family=FAMILY_ISO, nu=0.5, nspace=0,

@@ -17,26 +17,21 @@ __device__ unsigned long long section_cycles[kSections];
 #endif
 
 // Instantiations live in vecchia_inst_k*.hip (compiled in parallel).
-#define VEC_DECLARE(K, PC, NG)                                                                 \
-  extern template hipError_t launch_sums<K, PC, NG>(                                           \
-      int, hipStream_t, int, int, int, int, const double*, const int32_t*, const double*,     \
-      const double*, const double*, int64_t, int64_t, double*, int32_t*);
-#define VEC_DECLARE_K(K) \
-  VEC_DECLARE(K, 1, 1)   \
-  VEC_DECLARE(K, 2, 1)   \
-  VEC_DECLARE(K, 3, 1)   \
-  VEC_DECLARE(K, 1, 2)   \
-  VEC_DECLARE(K, 2, 2)   \
-  VEC_DECLARE(K, 3, 2)
-VEC_DECLARE_K(11)
-VEC_DECLARE_K(21)
-VEC_DECLARE_K(31)
+#define VEC_DECLARE(K, PC, NG, MODE) extern template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE)
+#define VEC_DECLARE_K(K)                   \
+  VECCHIA_FOR_MODES(VEC_DECLARE, K, 1);    \
+  VECCHIA_FOR_MODES(VEC_DECLARE, K, 2);    \
+  VECCHIA_FOR_MODES(VEC_DECLARE, K, 3)
+VEC_DECLARE_K(11);
+VEC_DECLARE_K(21);
+VEC_DECLARE_K(31);
 
-#define VEC_ROW(K)                                                                              \
-  {{launch_sums<K, 1, 1>, launch_sums<K, 1, 2>},                                               \
-   {launch_sums<K, 2, 1>, launch_sums<K, 2, 2>},                                               \
-   {launch_sums<K, 3, 1>, launch_sums<K, 3, 2>}}
-static const launch_fn kLaunch[kNumK][3][2] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31)};
+// kLaunch[K index][p - 1][space-time][mode]
+#define VEC_NG(K, PC, NG) \
+  {launch_sums<K, PC, NG, kModeSums>, launch_sums<K, PC, NG, kModeAdjoint>, launch_sums<K, PC, NG, kModeLoglik>}
+#define VEC_PC(K, PC) {VEC_NG(K, PC, 1), VEC_NG(K, PC, 2)}
+#define VEC_ROW(K) {VEC_PC(K, 1), VEC_PC(K, 2), VEC_PC(K, 3)}
+static const launch_fn kLaunch[kNumK][3][2][3] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31)};
 
 constexpr int kBlocksPerCU = 8;
 constexpr int kMaxP = 3;
@@ -222,40 +217,63 @@ __global__ void fisher_kernel(int P, int p, const double* __restrict__ out,
   for (int j = 0; j < P; ++j) covparms[j] = th[j] * exp(g[j] * scale);
 }
 
+// Loglik at the given beta and the scaled gradient from the adjoint sums
+// (logdet, r'S r, grad[P]).
+__global__ void adjoint_finalize_kernel(int64_t n, int P, const double* __restrict__ raw,
+                                        const double* __restrict__ grad_out,
+                                        double* __restrict__ loglik, double* __restrict__ dcovparms,
+                                        int32_t* __restrict__ status) {
+  if (threadIdx.x != 0) return;
+  const double ll = -0.5 * ((double)n * log(2.0 * M_PI) + raw[0] + raw[1]);
+  const double go = grad_out ? grad_out[0] : 1.0;
+  bool finite = __builtin_isfinite(ll);
+  for (int j = 0; j < P; ++j) {
+    dcovparms[j] = go * raw[2 + j];
+    finite = finite && __builtin_isfinite(raw[2 + j]);
+  }
+  if (loglik) loglik[0] = ll;
+  if (!finite) atomicOr(&status[0], VEC_FLAG_NONFINITE);
+}
+
 static int hip_code(hipError_t e) { return e == hipSuccess ? VEC_OK : VEC_EHIP; }
 
-static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, const double* locs,
+// Doubles per neighbourhood-sum vector of one kernel mode.
+static int nraw_for(const Dims& dm, int mode) { return nraw_mode(mode, dm.p, dm.P); }
+
+static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, const double* locs,
                               const int32_t* NN, const double* y, const double* X,
-                              const double* covparms, int64_t i0, int64_t i1, double* partials,
-                              size_t partials_bytes, int* grid_out, int32_t* status,
-                              hipStream_t st) {
+                              const double* covparms, const double* beta, int64_t i0, int64_t i1,
+                              double* partials, size_t partials_bytes, int* grid_out,
+                              int32_t* status, hipStream_t st) {
   const int grid = grid_for(i1 - i0);
   *grid_out = grid;
   if (grid == 0) return VEC_OK;
-  const size_t need = (size_t)grid * dm.nraw * sizeof(double);
+  const size_t need = (size_t)grid * nraw_for(dm, mode) * sizeof(double);
   if (!partials || partials_bytes < need) return VEC_EWORKSPACE;
   const int pc = dm.p - 1, ng = (pb->family == VEC_FAMILY_SPACETIME) ? 1 : 0;
-  hipError_t e = kLaunch[dm.kidx][pc][ng](grid, st, pb->m, pb->d, pb->nspace, dm.nu, locs, NN, y,
-                                          X, covparms, i0, i1, partials, status);
+  hipError_t e = kLaunch[dm.kidx][pc][ng][mode](grid, st, pb->m, pb->d, pb->nspace, dm.nu, locs,
+                                                NN, y, X, covparms, beta, i0, i1, partials, status);
   return hip_code(e);
 }
 
-static int enqueue_sums(const vec_problem* pb, const Dims& dm, const double* locs,
+// Kernel pass over [i0, i1) followed by the fixed-order reduction into raw.
+static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const double* locs,
                         const int32_t* NN, const double* y, const double* X,
-                        const double* covparms, int64_t i0, int64_t i1, double* raw,
-                        void* workspace, size_t workspace_bytes, int32_t* status,
+                        const double* covparms, const double* beta, int64_t i0, int64_t i1,
+                        double* raw, void* workspace, size_t workspace_bytes, int32_t* status,
                         hipStream_t st) {
   const int64_t total = i1 - i0;
+  const int nraw = nraw_for(dm, mode);
   if (total == 0) {
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, raw, dm.nraw, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, raw, nraw, 0.0);
     return hip_code(hipGetLastError());
   }
   double* partials = static_cast<double*>(workspace);
   int grid = 0;
-  int rc = enqueue_block_sums(pb, dm, locs, NN, y, X, covparms, i0, i1, partials, workspace_bytes,
-                              &grid, status, st);
+  int rc = enqueue_block_sums(pb, dm, mode, locs, NN, y, X, covparms, beta, i0, i1, partials,
+                              workspace_bytes, &grid, status, st);
   if (rc != VEC_OK) return rc;
-  hipLaunchKernelGGL(reduce_kernel, dim3(dm.nraw), dim3(256), 0, st, partials, grid, dm.nraw, raw);
+  hipLaunchKernelGGL(reduce_kernel, dim3(nraw), dim3(256), 0, st, partials, grid, nraw, raw);
   return hip_code(hipGetLastError());
 }
 
@@ -297,8 +315,8 @@ int vec_raw_sums(const vec_problem* pb, const double* locs, const int32_t* NNarr
   if (!dims_of(pb, &dm)) return VEC_EINVAL;
   if (i0 < 0 || i1 < i0 || i1 > pb->n) return VEC_EINVAL;
   if (!locs || !NNarray || !y || !X || !covparms || !raw || !status) return VEC_EINVAL;
-  return enqueue_sums(pb, dm, locs, NNarray, y, X, covparms, i0, i1, raw, workspace,
-                      workspace_bytes, status, static_cast<hipStream_t>(stream));
+  return enqueue_sums(pb, dm, kModeSums, locs, NNarray, y, X, covparms, nullptr, i0, i1, raw,
+                      workspace, workspace_bytes, status, static_cast<hipStream_t>(stream));
 }
 
 int vec_block_sums(const vec_problem* pb, const double* locs, const int32_t* NNarray,
@@ -310,8 +328,9 @@ int vec_block_sums(const vec_problem* pb, const double* locs, const int32_t* NNa
   if (i0 < 0 || i1 < i0 || i1 > pb->n) return VEC_EINVAL;
   if (!locs || !NNarray || !y || !X || !covparms || !status) return VEC_EINVAL;
   int grid = 0;
-  int rc = enqueue_block_sums(pb, dm, locs, NNarray, y, X, covparms, i0, i1, partials,
-                              partials_bytes, &grid, status, static_cast<hipStream_t>(stream));
+  int rc = enqueue_block_sums(pb, dm, kModeSums, locs, NNarray, y, X, covparms, nullptr, i0, i1,
+                              partials, partials_bytes, &grid, status,
+                              static_cast<hipStream_t>(stream));
   *nblocks = grid;
   return rc;
 }
@@ -333,6 +352,46 @@ int vecchia_loglik_grad_info(const vec_problem* pb, const double* locs, const in
                         workspace_bytes, status, stream);
   if (rc != VEC_OK) return rc;
   return vec_combine(pb, raw, out, status, stream);
+}
+
+int vec_loglik(const vec_problem* pb, const double* locs, const int32_t* NNarray, const double* y,
+               const double* X, const double* covparms, double* raw, double* out, void* workspace,
+               size_t workspace_bytes, int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm)) return VEC_EINVAL;
+  if (!locs || !NNarray || !y || !X || !covparms || !raw || !out || !status) return VEC_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = enqueue_sums(pb, dm, kModeLoglik, locs, NNarray, y, X, covparms, nullptr, 0, pb->n, raw,
+                        workspace, workspace_bytes, status, st);
+  if (rc != VEC_OK) return rc;
+  // the combine step with no covariance parameters: loglik, betahat, betainfo
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, 0, raw, out, status);
+  return hip_code(hipGetLastError());
+}
+
+int vec_loglik_adjoint(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                       const double* y, const double* X, const double* covparms,
+                       const double* betahat, const double* grad_out, double* loglik,
+                       double* dcovparms, void* workspace, size_t workspace_bytes,
+                       int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm)) return VEC_EINVAL;
+  if (!locs || !NNarray || !y || !X || !covparms || !betahat || !dcovparms || !status)
+    return VEC_EINVAL;
+  if (!workspace) return VEC_EWORKSPACE;
+  // partials first, the reduced vector (2 + P doubles) at the end
+  const int nraw = nraw_for(dm, kModeAdjoint);
+  const int grid = grid_for(pb->n);
+  const size_t part_bytes = (size_t)grid * nraw * sizeof(double);
+  if (workspace_bytes < part_bytes + nraw * sizeof(double)) return VEC_EWORKSPACE;
+  double* raw = reinterpret_cast<double*>(static_cast<char*>(workspace) + part_bytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = enqueue_sums(pb, dm, kModeAdjoint, locs, NNarray, y, X, covparms, betahat, 0, pb->n,
+                        raw, workspace, part_bytes, status, st);
+  if (rc != VEC_OK) return rc;
+  hipLaunchKernelGGL(adjoint_finalize_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.P, raw,
+                     grad_out, loglik, dcovparms, status);
+  return hip_code(hipGetLastError());
 }
 
 int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms,
@@ -364,7 +423,8 @@ static int one_iteration(const vec_problem* pb, const Dims& dm, const double* lo
                          const int32_t* NN, const double* y, const double* X, double* covparms,
                          double max_step, double* raw, double* out, void* ws, size_t wsb,
                          int32_t* status, hipStream_t st) {
-  int rc = enqueue_sums(pb, dm, locs, NN, y, X, covparms, 0, pb->n, raw, ws, wsb, status, st);
+  int rc = enqueue_sums(pb, dm, kModeSums, locs, NN, y, X, covparms, nullptr, 0, pb->n, raw, ws,
+                        wsb, status, st);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, dm.P, raw, out, status);
   hipLaunchKernelGGL(fisher_kernel, dim3(1), dim3(64), 0, st, dm.P, dm.p, out, covparms, status,

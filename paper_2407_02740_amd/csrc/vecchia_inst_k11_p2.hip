@@ -1,12 +1,9 @@
 // Instantiations of the fused per-neighbourhood kernel for K = 11
-// (m <= 10) and p = 2 covariates, isotropic and space-time ranges.
+// (m <= 10) and p = 2 covariates: isotropic and space-time ranges, each in
+// the sums, adjoint and loglik-only modes.
 #include "vecchia_kernels.hpp"
 
 namespace vecchia {
-template hipError_t launch_sums<11, 2, 1>(int, hipStream_t, int, int, int, int, const double*,
-                                          const int32_t*, const double*, const double*,
-                                          const double*, int64_t, int64_t, double*, int32_t*);
-template hipError_t launch_sums<11, 2, 2>(int, hipStream_t, int, int, int, int, const double*,
-                                          const int32_t*, const double*, const double*,
-                                          const double*, int64_t, int64_t, double*, int32_t*);
+#define VECCHIA_INSTANTIATE(K, PC, NG, MODE) template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE)
+VECCHIA_FOR_MODES(VECCHIA_INSTANTIATE, 11, 2);
 }  // namespace vecchia

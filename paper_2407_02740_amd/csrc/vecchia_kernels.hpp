@@ -100,6 +100,17 @@ constexpr int kThreads = 64;
 // nu codes: 0 -> 1/2, 1 -> 3/2, 2 -> 5/2
 constexpr int nraw_of(int p, int P) { return 2 + p * p + p + P * (2 + p * p + p) + P * P; }
 
+// What one pass of the fused kernel accumulates per neighbourhood.
+//   kModeSums     the loglik, gradient and Fisher-information sums
+//                 (nraw_of(p, P) doubles, layout of vec_raw_sums).
+//   kModeAdjoint  the gradient at a given beta by the reverse-mode
+//                 expression (logdet, r'S r, grad[P]; r = y - X beta).
+//   kModeLoglik   the sums of Algorithm 1 alone (logdet, ySy, XSX, ySX).
+constexpr int kModeSums = 0, kModeAdjoint = 1, kModeLoglik = 2;
+constexpr int nraw_mode(int mode, int p, int P) {
+  return mode == kModeSums ? nraw_of(p, P) : (mode == kModeAdjoint ? 2 + P : nraw_of(p, 0));
+}
+
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
   if constexpr (B < E) {
@@ -217,19 +228,23 @@ struct CovCoef {
   double ir[2];         // 1/range per group
 };
 
-template <int K, int PC, int NG>
+template <int K, int PC, int NG, int MODE>
 __global__ __launch_bounds__(kThreads) void sums_kernel(
     const int m, const int d, const int nspace, const int nu, const double* __restrict__ locs,
     const int32_t* __restrict__ NN, const double* __restrict__ y, const double* __restrict__ X,
-    const double* __restrict__ covparms, const int64_t i0, const int64_t i1,
-    double* __restrict__ partials, int32_t* __restrict__ status) {
+    const double* __restrict__ covparms, const double* __restrict__ beta, const int64_t i0,
+    const int64_t i1, double* __restrict__ partials, int32_t* __restrict__ status) {
   using G = Geo<K>;
   constexpr int NS = G::NS;
   constexpr int KP = G::KP;
   constexpr int NL = G::NL;
   constexpr int P = NG + 2;   // sigma2, ranges, tau2
   constexpr int NR = NG + 1;  // parameters whose w has entries above the self row
-  constexpr int NRAW = nraw_of(PC, P);
+  constexpr bool kFull = MODE == kModeSums;
+  constexpr bool kAdj = MODE == kModeAdjoint;
+  constexpr bool kLik = MODE == kModeLoglik;
+  constexpr int NRAW = nraw_mode(MODE, PC, P);
+  constexpr int RC = kAdj ? 1 : 1 + PC;  // right-hand sides of the forward substitution
   constexpr int LPN = K * (K - 1) / 2;  // strictly lower L, index r(r-1)/2 + c
   static_assert(K % 16 != 0, "rows >= K serve as spare rows");
   constexpr int SS = G::slot_of(K - 1);
@@ -242,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   constexpr int RZ = 0, RU = 4;
   constexpr int RS = 6;  // row stride, 16-byte aligned
   __shared__ double rec[kGroupsPerBlock][KP][RS];
-  __shared__ double Lp[kGroupsPerBlock][LPN + 16];  // + one write sink per lane
+  __shared__ double Lp[kGroupsPerBlock][kLik ? 1 : LPN + 16];  // + one write sink per lane
   __shared__ double acc[kGroupsPerBlock][NRAW];
   // running product of conditional variances (mantissa, exponent)
   __shared__ double vprod[kGroupsPerBlock][2];
@@ -250,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   // from which every range derivative of the pair follows (last slot: sink
   // for diagonal entries)
   constexpr int NPAIR = KP * (KP - 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][NPAIR + 2];  // + write sink, + zero
+  __shared__ double sfv[kGroupsPerBlock][kLik ? 2 : NPAIR + 2];  // + write sink, + zero
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -268,9 +283,12 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   cf.a1 = (nu == 2) ? 1.0 / 3.0 : 0.0;
   cf.a2 = (nu == 0) ? 1.0 : 0.0;
   const double inv_sigma2 = 1.0 / cf.sigma2;
+  double bt[PC];
+#pragma unroll
+  for (int t = 0; t < PC; ++t) bt[t] = kAdj ? beta[t] : 0.0;
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
-  if (threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
+  if (!kLik && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
   __shared__ double exptab[64];
   static_assert(kThreads == 64, "one table entry per thread");
   exptab[threadIdx.x] = kExp2Tab[threadIdx.x];
@@ -354,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     // any other row is exp(-h) = 0 exactly, so the padding block decouples
     // with no masking anywhere below.
     double zo[NS][4];
-    double rhs[1 + PC][NS];
+    double rhs[RC][NS];
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
@@ -379,9 +397,17 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         zo[s][k] = has ? zc[k] : ((k == 0) ? kFar * (double)(1 + r) : 0.0);
         rec[grp][r][RZ + k] = zo[s][k];
       }
-      rhs[0][s] = has ? yv[s] : 0.0;
+      if constexpr (kAdj) {
+        // residual at the given beta
+        double rv = yv[s];
 #pragma unroll
-      for (int t = 0; t < PC; ++t) rhs[1 + t][s] = has ? xv[s][t] : 0.0;
+        for (int t = 0; t < PC; ++t) rv = __builtin_fma(-xv[s][t], bt[t], rv);
+        rhs[0][s] = has ? rv : 0.0;
+      } else {
+        rhs[0][s] = has ? yv[s] : 0.0;
+#pragma unroll
+        for (int t = 0; t < PC; ++t) rhs[1 + t][s] = has ? xv[s][t] : 0.0;
+      }
     });
     // next NNarray row, in flight during phase 1
     if (more) fetch_ids(inext, l, idn, badn);
@@ -427,8 +453,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       const double sE1 = cf.sigma2 * ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
       const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
       const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
-      sfv[grp][idx0] = (NG == 1) ? sF0 * h20 * cf.ir[0] : sF0;
-      sfv[grp][idx1] = (NG == 1) ? sF1 * h21 * cf.ir[0] : sF1;
+      if constexpr (!kLik) {
+        sfv[grp][idx0] = (NG == 1) ? sF0 * h20 * cf.ir[0] : sF0;
+        sfv[grp][idx1] = (NG == 1) ? sF1 * h21 * cf.ir[0] : sF1;
+      }
       v0 = sE0 * __builtin_fma(hh0, __builtin_fma(hh0, cf.c2, cf.c1), 1.0);
       v1 = sE1 * __builtin_fma(hh1, __builtin_fma(hh1, cf.c2, cf.c1), 1.0);
     };
@@ -617,14 +645,16 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     // ---------------- ut = Lt^{-T} e_last via Lt in LDS ----------------
     VEC_MARK("backsolve");
     VEC_TMARK(6);
-    sfor<0, NS>([&](auto s_) {
-      constexpr int s = s_.value;
-      const int r = row_of(s, l);
-      sfor<0, G::len(s)>([&](auto c_) {
-        constexpr int c = c_.value;
-        Lp[grp][(c < r && r < K) ? r * (r - 1) / 2 + c : LPN + l] = A[G::off(s) + c];
+    if constexpr (!kLik) {
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        const int r = row_of(s, l);
+        sfor<0, G::len(s)>([&](auto c_) {
+          constexpr int c = c_.value;
+          Lp[grp][(c < r && r < K) ? r * (r - 1) / 2 + c : LPN + l] = A[G::off(s) + c];
+        });
       });
-    });
+    }
     double uu[NS];
     sfor<0, NS>([&](auto s_) { uu[s_.value] = (row_of(s_.value, l) == K - 1) ? 1.0 : 0.0; });
     wave_lds_fence();
@@ -643,31 +673,43 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       });
     };
     constexpr int PF = (K < 3) ? K : 3;
-    double lvq[PF][NS];
-    sfor<0, PF>([&](auto x_) { lrow(std::integral_constant<int, K - 1 - x_.value>{}, lvq[x_.value]); });
-    // The back substitution (latency bound: one broadcast per step) runs
-    // interleaved with the independent forward substitution of y and X.
-    sfor<0, K>([&](auto x_) {
-      constexpr int x = x_.value;
+    // one step of x <- Lt^{-T} x at row r = K - 1 - x_ (Lt[r][.] prefetched
+    // PF steps ahead into the ring lvq)
+    auto back_step = [&](auto x_, double(&lvq)[PF][NS], double(&xv)[NS]) {
+      constexpr int x = decltype(x_)::value;
       constexpr int r = K - 1 - x;
       constexpr int sr = r / 16;
       constexpr int lr = G::lane_of(r);
       double lv[NS];
       sfor<0, NS>([&](auto s_) { lv[s_.value] = lvq[x % PF][s_.value]; });
       if constexpr (r - PF >= 0) lrow(std::integral_constant<int, r - PF>{}, lvq[x % PF]);
-      const double ur = bcast<lr>(uu[sr]);
+      const double xr = bcast<lr>(xv[sr]);
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (16 * s < r) uu[s] = __builtin_fma(-lv[s], ur, uu[s]);
+        if constexpr (16 * s < r) xv[s] = __builtin_fma(-lv[s], xr, xv[s]);
       });
-      fwd_step(x_, rhs);
-    });
-    // rhs = Lt^{-1} (y, X);  uu = Lt^{-T} e_last (u = uu / sqrt(d_last))
-    sfor<0, NS>([&](auto s_) {
-      constexpr int s = s_.value;
-      rec[grp][row_of(s, l)][RU] = uu[s];  // 0 for rows >= K
-    });
-    wave_lds_fence();
+    };
+    auto back_prefetch = [&](auto& lvq) {
+      sfor<0, PF>([&](auto x_) { lrow(std::integral_constant<int, K - 1 - x_.value>{}, lvq[x_.value]); });
+    };
+    if constexpr (kLik) {
+      fwd(rhs);
+    } else {
+      double lvq[PF][NS];
+      back_prefetch(lvq);
+      // The back substitution (latency bound: one broadcast per step) runs
+      // interleaved with the independent forward substitution of y and X.
+      sfor<0, K>([&](auto x_) {
+        back_step(x_, lvq, uu);
+        fwd_step(x_, rhs);
+      });
+      // rhs = Lt^{-1} (y, X);  uu = Lt^{-T} e_last (u = uu / sqrt(d_last))
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        rec[grp][row_of(s, l)][RU] = uu[s];  // 0 for rows >= K
+      });
+      wave_lds_fence();
+    }
 
     if (more) fetch_vals(inext, idn, zv, yv, xv);  // next neighbourhood, in flight until the next gather
     VEC_MARK("phase2");
@@ -677,7 +719,11 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     // from sfv (static offsets off the diagonal block, the zero slot on the
     // diagonal), u_b and z_b are uniform reads, one column ahead of use.
     // Pairs with a padding row have exp(-h) = 0 and add nothing.
+    // Adjoint: the back substitution alpha = Lt^{-T} D^{-1} yt (= Sigma^{-1} r)
+    // runs interleaved, one step per column.
     double gr[NG][NS];
+    double al[NS];
+    if constexpr (!kLik) {
     int base_a[NS];
     double zrow[NS][4];
     sfor<0, NS>([&](auto s_) {
@@ -713,10 +759,16 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
       });
     };
     {
+      double alq[PF][NS];
+      if constexpr (kAdj) {
+        sfor<0, NS>([&](auto s_) { al[s_.value] = rhs[0][s_.value] * idg[s_.value]; });
+        back_prefetch(alq);
+      }
       double ubn, zbn[4], Svn[NS];
       col_load(std::integral_constant<int, 0>{}, ubn, zbn, Svn);
       sfor<0, K>([&](auto b_) {
         constexpr int b = b_.value;
+        if constexpr (kAdj) back_step(b_, alq, al);
         double ub = ubn, zb[4], Sv[NS];
 #pragma unroll
         for (int k = 0; k < 4; ++k) zb[k] = zbn[k];
@@ -748,7 +800,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         gr[1][s_.value] *= cf.ir[1];
       });
     }
+    }  // !kLik
 
+    if constexpr (kFull) {
     VEC_MARK("w_solve");
     VEC_TMARK(8);
     // ---------------- w = L^{-1} (dSigma_j u) ----------------
@@ -862,6 +916,83 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
         atomicMin(&status[1], (int32_t)i);
       }
     }
+    } else if constexpr (kAdj) {
+    VEC_MARK("adjoint");
+    // ---------------- reverse-mode gradient ----------------
+    // With v = d_q and e = yt_q (conditional variance and residual of the
+    // self row), the neighbourhood's term -1/2 (log v + e^2 / v) has
+    // derivative, for dSigma_j,
+    //   -1/2 [ (ut' dSigma_j ut) (1 + e^2/v) / v - 2 e (alpha' dSigma_j ut) / v ],
+    // where ut = Lt^{-T} e_last and alpha = Sigma^{-1} r.  Range parameters
+    // use g_j = dSigma_j ut from phase 2, tau2 uses g = sigma2 ut and sigma2
+    // reduces to -1/2 (1 - e^2/v) / sigma2 (Sigma ut = v e_last).
+    constexpr int ND = 2 * NG + 2;
+    double dots[ND];
+    sfor<0, ND>([&](auto e_) { dots[e_.value] = 0.0; });
+    sfor<0, NS>([&](auto s_) {
+      constexpr int s = s_.value;
+      sfor<0, NG>([&](auto g_) {
+        constexpr int g = g_.value;
+        dots[2 * g] = __builtin_fma(uu[s], gr[g][s], dots[2 * g]);
+        dots[2 * g + 1] = __builtin_fma(al[s], gr[g][s], dots[2 * g + 1]);
+      });
+      dots[2 * NG] = __builtin_fma(uu[s], uu[s], dots[2 * NG]);
+      dots[2 * NG + 1] = __builtin_fma(al[s], uu[s], dots[2 * NG + 1]);
+    });
+    sfor<0, ND>([&](auto e_) { dots[e_.value] = row_allreduce(dots[e_.value]); });
+    if (active && l == LS) {
+      const double iv = idg[SS];
+      const double e = rhs[0][SS];
+      const double e2v = e * e * iv;
+      const double c1 = (1.0 + e2v) * iv, c2 = 2.0 * e * iv;
+      const bool nonfinite = !(__builtin_isfinite(e2v));
+      double* ac = acc[grp];
+      int ex;
+      vprod[grp][0] = frexp(vprod[grp][0] * vself, &ex);
+      vprod[grp][1] += (double)ex;
+      ac[1] += e2v;
+      ac[2] += -0.5 * (1.0 - e2v) * inv_sigma2;
+      sfor<0, NG>([&](auto g_) {
+        constexpr int g = g_.value;
+        ac[3 + g] += -0.5 * (dots[2 * g] * c1 - c2 * dots[2 * g + 1]);
+      });
+      ac[1 + P] += -0.5 * cf.sigma2 * (dots[2 * NG] * c1 - c2 * dots[2 * NG + 1]);
+      static_assert(2 + P == NRAW, "adjoint layout");
+      const int flags = (notpd ? 1 : 0) | (nonfinite ? 4 : 0);
+      if (flags) {
+        atomicOr(&status[0], flags);
+        atomicMin(&status[1], (int32_t)i);
+      }
+    }
+    } else {
+    VEC_MARK("loglik");
+    // ---------------- sums of Algorithm 1 ----------------
+    if (active && l == LS) {
+      const double sq = rsqrt_refined(vself);
+      const double Lyq = rhs[0][SS] * sq;
+      double LXq[PC];
+      bool nonfinite = !(__builtin_isfinite(Lyq));
+      sfor<0, PC>([&](auto t_) {
+        LXq[t_.value] = rhs[1 + t_.value][SS] * sq;
+        nonfinite |= !(__builtin_isfinite(LXq[t_.value]));
+      });
+      double* ac = acc[grp];
+      int ex;
+      vprod[grp][0] = frexp(vprod[grp][0] * vself, &ex);
+      vprod[grp][1] += (double)ex;
+      ac[1] += Lyq * Lyq;
+      sfor<0, PC>([&](auto s_) {
+        sfor<0, PC>([&](auto t_) { ac[2 + s_.value * PC + t_.value] += LXq[s_.value] * LXq[t_.value]; });
+        ac[2 + PC * PC + s_.value] += Lyq * LXq[s_.value];
+      });
+      static_assert(2 + PC * PC + PC == NRAW, "loglik layout");
+      const int flags = (notpd ? 1 : 0) | (nonfinite ? 4 : 0);
+      if (flags) {
+        atomicOr(&status[0], flags);
+        atomicMin(&status[1], (int32_t)i);
+      }
+    }
+    }
     VEC_TMARK(11);
     if (active && (badnn || badval)) {
       atomicOr(&status[0], (badnn ? 2 : 0) | (badval ? 4 : 0));
@@ -883,19 +1014,34 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
 }
 
 // Host-side launcher of one instantiation.
-template <int K, int PC, int NG>
+template <int K, int PC, int NG, int MODE>
 hipError_t launch_sums(int grid, hipStream_t stream, int m, int d, int nspace, int nu,
                        const double* locs, const int32_t* NN, const double* y, const double* X,
-                       const double* covparms, int64_t i0, int64_t i1, double* partials,
-                       int32_t* status) {
-  hipLaunchKernelGGL((sums_kernel<K, PC, NG>), dim3(grid), dim3(kThreads), 0, stream, m, d,
-                     nspace, nu, locs, NN, y, X, covparms, i0, i1, partials, status);
+                       const double* covparms, const double* beta, int64_t i0, int64_t i1,
+                       double* partials, int32_t* status) {
+  hipLaunchKernelGGL((sums_kernel<K, PC, NG, MODE>), dim3(grid), dim3(kThreads), 0, stream, m, d,
+                     nspace, nu, locs, NN, y, X, covparms, beta, i0, i1, partials, status);
   return hipGetLastError();
 }
 
 using launch_fn = hipError_t (*)(int, hipStream_t, int, int, int, int, const double*,
                                  const int32_t*, const double*, const double*, const double*,
-                                 int64_t, int64_t, double*, int32_t*);
+                                 const double*, int64_t, int64_t, double*, int32_t*);
+
+// Explicit instantiation of the launchers of one K and p (both range
+// layouts, all three modes), used by the per-(K, p) translation units.
+#define VECCHIA_LAUNCH_SIG(K, PC, NG, MODE)                                                     \
+  hipError_t launch_sums<K, PC, NG, MODE>(int, hipStream_t, int, int, int, int, const double*,  \
+                                          const int32_t*, const double*, const double*,        \
+                                          const double*, const double*, int64_t, int64_t,      \
+                                          double*, int32_t*)
+#define VECCHIA_FOR_MODES(X, K, PC) \
+  X(K, PC, 1, 0);                   \
+  X(K, PC, 2, 0);                   \
+  X(K, PC, 1, 1);                   \
+  X(K, PC, 2, 1);                   \
+  X(K, PC, 1, 2);                   \
+  X(K, PC, 2, 2)
 
 // Instantiated K values (K >= m + 1 is padded with identity rows).
 constexpr int kNumK = 3;

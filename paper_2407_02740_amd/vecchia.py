@@ -69,6 +69,12 @@ def lib():
         L.vecchia_loglik_grad_info.restype = ctypes.c_int
         L.vecchia_loglik_grad_info.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                            ctypes.c_size_t, _VP, _VP]
+        L.vec_loglik.restype = ctypes.c_int
+        L.vec_loglik.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP,
+                                 _VP]
+        L.vec_loglik_adjoint.restype = ctypes.c_int
+        L.vec_loglik_adjoint.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                         ctypes.c_size_t, _VP, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
         L.vec_fisher_fit.restype = ctypes.c_int
@@ -219,6 +225,48 @@ class Vecchia:
             self.check_status("vecchia_loglik_grad_info")
         return self.out
 
+    def loglik(self, covparms, check: bool = True) -> torch.Tensor:
+        """Profile log-likelihood alone (the sums of Algorithm 1 and the
+        combine step): a new tensor [loglik, betahat[p], betainfo[p][p]]."""
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        ws = self.workspace()
+        out = torch.empty(1 + self.p + self.p * self.p, dtype=torch.float64, device=self.device)
+        _check(lib().vec_loglik(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), self.raw.data_ptr(),
+            out.data_ptr(), ws.data_ptr(), ws.numel() * 8, self.status.data_ptr(), _stream()),
+            "vec_loglik")
+        if check:
+            self.check_status("vec_loglik")
+        return out
+
+    def loglik_adjoint(self, covparms, betahat, grad_out: torch.Tensor | None = None,
+                       check: bool = True):
+        """Reverse-mode gradient of the log-likelihood at the mean vector
+        betahat, each neighbourhood's factor recomputed: returns new tensors
+        (loglik at betahat, grad_out * d loglik / d covparms)."""
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        beta = torch.as_tensor(betahat, dtype=torch.float64).to(self.device).contiguous()
+        if beta.numel() != self.p:
+            raise ValueError(f"betahat needs {self.p} entries")
+        go = 0
+        if grad_out is not None:
+            grad_out = grad_out.to(device=self.device, dtype=torch.float64).contiguous()
+            go = _dev(grad_out, torch.float64, "grad_out")
+        ws = self.workspace()
+        ll = torch.empty(1, dtype=torch.float64, device=self.device)
+        dcp = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        _check(lib().vec_loglik_adjoint(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), beta.data_ptr(), go,
+            ll.data_ptr(), dcp.data_ptr(), ws.data_ptr(), ws.numel() * 8,
+            self.status.data_ptr(), _stream()), "vec_loglik_adjoint")
+        if check:
+            self.check_status("vec_loglik_adjoint")
+        return ll, dcp
+
     def fisher_update(self, covparms: torch.Tensor, max_step: float = 1.0):
         _check(lib().vec_fisher_update(ctypes.byref(self.pb), self.out.data_ptr(),
                                        _dev(covparms, torch.float64, "covparms"),
@@ -238,3 +286,35 @@ class Vecchia:
         if check:
             self.check_status("vec_fisher_fit")
         return covparms
+
+
+class VecchiaLoglik(torch.autograd.Function):
+    """Profile log-likelihood as a differentiable function of covparms.
+
+    forward:  the loglik-only pass (betahat comes with it).
+    backward: the adjoint pass at that betahat, scaled by grad_output on the
+              device.  Because betahat maximises the likelihood over the mean
+              parameters, the derivative at fixed betahat is the derivative of
+              the profile likelihood.
+    Only covparms receives a gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, covparms: torch.Tensor, ev: "Vecchia", check: bool = True):
+        cp = covparms.detach().to(device=ev.device, dtype=torch.float64).contiguous()
+        out = ev.loglik(cp, check=check)
+        ctx.ev = ev
+        ctx.check = check
+        ctx.save_for_backward(cp, out[1:1 + ev.p].clone())
+        return out[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_output):
+        cp, beta = ctx.saved_tensors
+        _, dcp = ctx.ev.loglik_adjoint(cp, beta, grad_output.reshape(1), check=ctx.check)
+        return dcp, None, None
+
+
+def vecchia_loglik(ev: Vecchia, covparms: torch.Tensor, check: bool = True) -> torch.Tensor:
+    """Differentiable profile log-likelihood (see VecchiaLoglik)."""
+    return VecchiaLoglik.apply(covparms, ev, check)

@@ -1,0 +1,185 @@
+"""Parity of the loglik-only and adjoint (reverse-mode) entry points, and of
+the torch.autograd.Function built on them, with the CPU oracle.
+
+Tolerances as for the forward path:
+  loglik   |d| <= 1e-10 |loglik|
+  grad_j   |d| <= 1e-8 max(|grad_j|, sqrt(I_jj))   (I from the oracle)
+  betahat  |d| <= 1e-8 (|beta_t| + 1/sqrt(XSX_tt))
+The reference gradient at a fixed beta is the oracle's forward-mode
+expression (oracle.at_beta); at beta = betahat it is the profile gradient.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_02740_amd import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2407_02740_amd import vecchia as V  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _problem(n, m, family, nu, p, seed):
+    rng = np.random.default_rng(seed)
+    d = 2 if family == V.FAMILY_ISO else 3
+    locs = rng.random((n, d))
+    locs = locs[S.maxmin_exact(locs)]
+    NN = S.find_ordered_nn(locs, m)
+    y = rng.standard_normal(n) + 0.3 * np.sin(7 * locs[:, 0])
+    X = np.column_stack([np.ones(n)] + [rng.standard_normal(n) for _ in range(p - 1)])
+    cp = np.array((1.3, 0.15, 0.05)) if family == V.FAMILY_ISO else np.array((1.1, 0.3, 0.5, 0.1))
+    return dict(locs=locs, NN=NN, y=y, X=X, covparms=cp, family=family, nu=nu,
+                nspace=(2 if family == V.FAMILY_SPACETIME else 0), n=n, m=m, p=p)
+
+
+def _oracle(w):
+    raw = oracle.raw_sums(w["locs"], w["NN"], w["y"], w["X"], w["covparms"], w["family"], w["nu"],
+                          w["nspace"], threads=8)
+    P = oracle.nparms(w["family"])
+    return raw, oracle.combine(raw, w["n"], w["p"], P)
+
+
+def _ev(w):
+    return V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], w["family"], w["nu"], w["nspace"])
+
+
+def _check_grad(got, ref, info, tag):
+    sd = np.sqrt(np.abs(np.diag(info)))
+    err = np.abs(np.asarray(got) - ref)
+    assert np.all(err <= 1e-8 * np.maximum(np.abs(ref), sd)), (tag, got, ref)
+
+
+CASES = [(V.FAMILY_ISO, 0.5, 1), (V.FAMILY_ISO, 1.5, 3), (V.FAMILY_ISO, 2.5, 2),
+         (V.FAMILY_SPACETIME, 0.5, 1), (V.FAMILY_SPACETIME, 2.5, 3)]
+
+
+@pytest.mark.parametrize("m", [0, 1, 7, 20, 30])
+@pytest.mark.parametrize("family,nu,p", CASES)
+def test_loglik_only_matches_oracle(m, family, nu, p):
+    w = _problem(701, m, family, nu, p, seed=300 + m)
+    _say(f"loglik-only m={m} fam={family} nu={nu} p={p}")
+    raw, ref = _oracle(w)
+    ev = _ev(w)
+    out = ev.loglik(w["covparms"]).cpu().numpy()
+    got_raw = ev.raw.cpu().numpy()[:2 + p * p + p]
+    np.testing.assert_allclose(got_raw, raw[:2 + p * p + p], rtol=0,
+                               atol=1e-9 * np.abs(raw[:2 + p * p + p]).max())
+    assert abs(out[0] - ref["loglik"]) <= 1e-10 * abs(ref["loglik"])
+    bscale = np.abs(ref["betahat"]) + 1.0 / np.sqrt(np.diag(ref["betainfo"]))
+    assert np.all(np.abs(out[1:1 + p] - ref["betahat"]) <= 1e-8 * bscale)
+    np.testing.assert_allclose(out[1 + p:].reshape(p, p), ref["betainfo"], rtol=1e-10)
+
+
+@pytest.mark.parametrize("m", [0, 1, 7, 20, 30])
+@pytest.mark.parametrize("family,nu,p", CASES)
+def test_adjoint_matches_oracle(m, family, nu, p):
+    w = _problem(701, m, family, nu, p, seed=400 + m)
+    _say(f"adjoint m={m} fam={family} nu={nu} p={p}")
+    raw, ref = _oracle(w)
+    ev = _ev(w)
+    P = ev.P
+    for beta in (ref["betahat"], ref["betahat"] + 0.5 - 0.2 * np.arange(p)):
+        at = oracle.at_beta(raw, w["n"], p, P, beta)
+        ll, dcp = ev.loglik_adjoint(w["covparms"], beta)
+        ll = float(ll.cpu()[0])
+        assert abs(ll - at["loglik"]) <= 1e-10 * abs(at["loglik"]), (ll, at["loglik"])
+        _check_grad(dcp.cpu().numpy(), at["grad"], ref["info"], f"m={m} beta={beta}")
+
+
+def test_adjoint_ragged_multi_tile_and_tiny():
+    for n, m in [(1, 0), (1, 5), (2, 3), (5, 30), (33, 30), (4099, 30)]:
+        w = _problem(n, m, V.FAMILY_SPACETIME, 1.5, 2, seed=n)
+        _say(f"adjoint n={n} m={m}")
+        raw, ref = _oracle(w)
+        ev = _ev(w)
+        at = oracle.at_beta(raw, n, 2, ev.P, ref["betahat"])
+        ll, dcp = ev.loglik_adjoint(w["covparms"], ref["betahat"])
+        assert abs(float(ll.cpu()[0]) - at["loglik"]) <= 1e-10 * abs(at["loglik"])
+        _check_grad(dcp.cpu().numpy(), at["grad"], ref["info"], f"n={n}")
+
+
+def test_grad_out_scales_the_gradient_exactly():
+    w = _problem(900, 15, V.FAMILY_ISO, 1.5, 1, seed=5)
+    ev = _ev(w)
+    beta = np.array([0.2])
+    _, g1 = ev.loglik_adjoint(w["covparms"], beta)
+    go = torch.tensor([-2.5], dtype=torch.float64, device="cuda")
+    _, g2 = ev.loglik_adjoint(w["covparms"], beta, go)
+    assert torch.equal(g2, g1 * -2.5)
+
+
+def test_adjoint_is_deterministic_and_reports_errors():
+    w = _problem(1500, 20, V.FAMILY_SPACETIME, 0.5, 1, seed=6)
+    ev = _ev(w)
+    a = ev.loglik_adjoint(w["covparms"], [0.1])[1].clone()
+    b = ev.loglik_adjoint(w["covparms"], [0.1])[1].clone()
+    assert torch.equal(a, b)
+    NN = w["NN"].copy()
+    NN[777, 3] = 900
+    bad = V.Vecchia(w["locs"], NN, w["y"], w["X"], w["family"], w["nu"], w["nspace"])
+    with pytest.raises(V.VecchiaError) as e:
+        bad.loglik_adjoint(w["covparms"], [0.1])
+    assert e.value.code == V.VEC_EBADNN and e.value.bad_i == 777
+
+
+def test_autograd_backward_equals_profile_gradient():
+    w = _problem(3000, 30, V.FAMILY_ISO, 2.5, 3, seed=8)
+    raw, ref = _oracle(w)
+    ev = _ev(w)
+    cp = torch.tensor(w["covparms"], dtype=torch.float64, device="cuda", requires_grad=True)
+    ll = V.vecchia_loglik(ev, cp)
+    assert abs(float(ll) - ref["loglik"]) <= 1e-10 * abs(ref["loglik"])
+    (3.0 * ll).backward()
+    _check_grad(cp.grad.cpu().numpy() / 3.0, ref["grad"], ref["info"], "autograd")
+
+
+def test_autograd_gradcheck():
+    w = _problem(300, 10, V.FAMILY_SPACETIME, 1.5, 1, seed=9)
+    ev = _ev(w)
+    cp = torch.tensor(w["covparms"], dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda c: V.vecchia_loglik(ev, c), (cp,), eps=1e-6, atol=1e-5,
+                                    rtol=1e-5)
+
+
+def test_autograd_composes_with_a_log_parametrisation():
+    """Gradient through a reparametrisation theta = exp(phi), the form a
+    first-order optimiser would use."""
+    w = _problem(2000, 15, V.FAMILY_SPACETIME, 0.5, 1, seed=10)
+    raw, ref = _oracle(w)
+    ev = _ev(w)
+    phi = torch.tensor(np.log(w["covparms"]), dtype=torch.float64, device="cuda",
+                       requires_grad=True)
+    ll = V.vecchia_loglik(ev, torch.exp(phi))
+    ll.backward()
+    _check_grad(phi.grad.cpu().numpy() / w["covparms"], ref["grad"], ref["info"], "log-param")
+
+
+@pytest.mark.skipif(os.environ.get("VECCHIA_SKIP_FULL") == "1", reason="full size skipped")
+def test_full_size_adjoint_equals_forward_gradient():
+    """At the 1,048,576-observation space-time workload: the adjoint at the
+    device's betahat against the forward-mode gradient of the fused kernel
+    (which the forward parity test checks against the oracle at this size),
+    and the loglik-only pass against the forward loglik."""
+    _say("full-size adjoint: generating")
+    w = S.satellite_spacetime()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ev = _ev(w)
+        fw = V.unpack_out(ev.loglik_grad_info(w["covparms"]).clone(), w["p"], ev.P)
+        lik = ev.loglik(w["covparms"]).cpu().numpy()
+        ll, dcp = ev.loglik_adjoint(w["covparms"], fw["betahat"])
+    torch.cuda.synchronize()
+    assert abs(lik[0] - fw["loglik"]) <= 1e-12 * abs(fw["loglik"])
+    assert abs(float(ll.cpu()[0]) - fw["loglik"]) <= 1e-12 * abs(fw["loglik"])
+    _check_grad(dcp.cpu().numpy(), fw["grad"], fw["info"], "full")

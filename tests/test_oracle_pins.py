@@ -16,7 +16,9 @@ so each part of the oracle is pinned by an independent route:
 * m = 0:           independent closed form;
 * identities:      sigma2 scaling identities, finite differences of the
                    log-likelihood, symmetry / PSD of the information,
-                   invariances, error reporting.
+                   invariances, error reporting;
+* fixed beta:      finite differences away from beta_hat, and the dense
+                   reverse-mode expression of the gradient.
 """
 
 import math
@@ -295,6 +297,81 @@ def test_gradient_matches_finite_differences(family, nu, p):
         lb = oracle.loglik_grad_info(locs, NN, y, X, b, family, nu, nspace=2)["loglik"]
         fd = (la - lb) / (2 * h)
         assert abs(fd - res["grad"][j]) <= 1e-6 * max(abs(fd), scale[j]), (j, fd, res["grad"][j])
+
+
+def _raw_and_dims(locs, NN, y, X, cp, family, nu, nspace):
+    raw = oracle.raw_sums(locs, NN, y, X, cp, family, nu, nspace)
+    return raw, len(y), X.shape[1], len(cp)
+
+
+@pytest.mark.parametrize("family,nu,p", [(ISO, 1.5, 2), (ST, 0.5, 1)])
+def test_at_beta_gradient_matches_finite_differences(family, nu, p):
+    """theta-gradient at a fixed beta away from beta_hat (where the envelope
+    argument no longer applies) against central differences of its loglik."""
+    d = 2 if family == ISO else 3
+    locs, NN, y, X, cp = _problem(300, 10, d=d, p=p, family=family, nu=nu, seed=21)
+    raw, n, p_, P = _raw_and_dims(locs, NN, y, X, cp, family, nu, 2)
+    bhat = oracle.combine(raw, n, p_, P)["betahat"]
+    beta = bhat + 0.7 + 0.3 * np.arange(p)
+    res = oracle.at_beta(raw, n, p_, P, beta)
+    prof = oracle.combine(raw, n, p_, P)
+    assert res["loglik"] < prof["loglik"]  # beta_hat maximises over beta
+    scale = np.sqrt(np.diag(prof["info"]))
+    for j in range(P):
+        h = 1e-5 * cp[j]
+        a, b = cp.copy(), cp.copy()
+        a[j] += h
+        b[j] -= h
+        la = oracle.at_beta(oracle.raw_sums(locs, NN, y, X, a, family, nu, 2), n, p_, P, beta)
+        lb = oracle.at_beta(oracle.raw_sums(locs, NN, y, X, b, family, nu, 2), n, p_, P, beta)
+        fd = (la["loglik"] - lb["loglik"]) / (2 * h)
+        assert abs(fd - res["grad"][j]) <= 1e-6 * max(abs(fd), scale[j]), (j, fd, res["grad"][j])
+
+
+def test_at_beta_equals_profile_at_betahat():
+    locs, NN, y, X, cp = _problem(250, 8, p=3, nu=2.5, seed=22)
+    raw, n, p, P = _raw_and_dims(locs, NN, y, X, cp, ISO, 2.5, 0)
+    prof = oracle.combine(raw, n, p, P)
+    res = oracle.at_beta(raw, n, p, P, prof["betahat"])
+    assert res["loglik"] == pytest.approx(prof["loglik"], rel=1e-13)
+    np.testing.assert_allclose(res["grad"], prof["grad"], rtol=1e-10,
+                               atol=1e-10 * np.abs(prof["grad"]).max())
+
+
+@pytest.mark.parametrize("family,nu", [(ISO, 0.5), (ISO, 2.5), (ST, 1.5)])
+def test_reverse_mode_expression_matches_at_beta(family, nu):
+    """The reverse-mode form of the per-neighbourhood gradient (the route the
+    adjoint kernel takes): with u = L^-T e_last, z = (L^-1 r)_last and
+    a = Sigma_s^-1 r_s padded with 0 for the self row, the adjoint of
+    Sigma_i is -1/2 [u u^T - z (u a^T + a u^T) - z^2 u u^T] and the gradient
+    is sum_i <adjoint_i, dSigma_i/dtheta_j>.  Dense per neighbourhood here,
+    against the forward-mode sums of at_beta."""
+    d = 2 if family == ISO else 3
+    nspace = 2
+    locs, NN, y, X, cp = _problem(80, 7, d=d, p=2, family=family, nu=nu, seed=23)
+    raw, n, p, P = _raw_and_dims(locs, NN, y, X, cp, family, nu, nspace)
+    beta = np.array([0.4, -0.9])
+    r = y - X @ beta
+    grad = np.zeros(P)
+    ll = 0.0
+    for i in range(n):
+        q = min(i, 7)
+        idx = list(NN[i, 1:q + 1]) + [i]  # self last
+        Si, dSi = oracle.cov_matrix(locs[idx], cp, family, nu, nspace)
+        L = np.linalg.cholesky(Si)
+        e_last = np.zeros(q + 1)
+        e_last[-1] = 1.0
+        u = np.linalg.solve(L.T, e_last)
+        z = np.linalg.solve(L, r[idx])[-1]
+        a = np.zeros(q + 1)
+        if q:
+            a[:q] = np.linalg.solve(Si[:q, :q], r[idx][:q])
+        adj = -0.5 * (np.outer(u, u) - z * (np.outer(u, a) + np.outer(a, u)) - z * z * np.outer(u, u))
+        grad += np.einsum("ab,jab->j", adj, dSi)
+        ll += -0.5 * (math.log(2 * math.pi) + 2 * math.log(L[-1, -1]) + z * z)
+    ref = oracle.at_beta(raw, n, p, P, beta)
+    assert ll == pytest.approx(ref["loglik"], rel=1e-12)
+    np.testing.assert_allclose(grad, ref["grad"], rtol=1e-10, atol=1e-10 * np.abs(ref["grad"]).max())
 
 
 def test_fisher_symmetric_positive_semidefinite():
