@@ -13,16 +13,26 @@ HIP graph.  Inputs are resident in device memory before timing starts.
 
 Prints one JSON line.  `value` is neighbourhoods per second (n x steps /
 elapsed).  `roofline` reports the fused kernel (timed alone with HIP events
-on its stream) against the FP64 vector peak; `cpu_baseline` times the CPU
-oracle on a bounded sample of the same workload.
+on its stream) against the FP64 vector peak; `traffic` is the HBM traffic per
+launch read from the committed rocprofv3 counter summary when that summary
+was taken on the current kernel source, else null.  `cpu_baseline` times the
+CPU oracle on a bounded sample of the same workload.
+
+`--workload batched_uneven` measures the batched persistent path instead:
+512 independent 2-D datasets (n uniform in [1000, 50000], m from
+{10, 20, 30, 40}, Matern covariance parameters and smoothness drawn per
+dataset), schedule picked by the autotuner, one step = one Fisher-scoring
+iteration of every dataset replayed from a captured HIP graph.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -31,7 +41,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "neighbourhoods/s (loglik+grad+Fisher), n=1M m=30; plain FP64 vs chosen form"
+METRIC_BATCHED = "neighbourhoods/s (loglik+grad+Fisher), 512 uneven datasets, m in {10,20,30,40}"
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PROFILE = os.path.join(ROOT, "profiles", "sums_kernel_satellite_spacetime_n1M_m30.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02740_amd", "csrc", f)
+                  for f in ("vecchia_kernels.hpp", "exp_table.inc")] + \
+                 [os.path.join(ROOT, "paper_2407_02740_amd", "build.py")]
 
 
 def log(msg):
@@ -50,21 +65,61 @@ def algorithmic_flops(k: int, d: int, p: int, R: int) -> int:
                + (R + 2) * (R + 3) * k)
 
 
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^([a-z_0-9]+):\s*(\S+)\s*$", text, flags=re.M))
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibration_kernel():
+    """A kernel of known HBM traffic for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: an in-place multiply of 512 MiB reads and writes 512 MiB."""
+    import torch
+
+    x = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        x.mul_(0.5)
+    torch.cuda.synchronize()
+    log("calibration: 2 x in-place multiply of 536870912 bytes")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--cpu-sample", type=int, default=262_144)
+    ap.add_argument("--cpu-sample", type=int, default=524_288)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 512 MiB device-to-device copy (a kernel of known traffic "
-                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--calibration", action="store_true",
+                    help="also run a kernel of known traffic (512 MiB read + 512 MiB write) "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--workload", default="satellite_spacetime",
+                    choices=["satellite_spacetime", "batched_uneven"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
         sys.exit(2)
+    if args.workload == "batched_uneven":
+        return bench_batched(args)
 
     import numpy as np
     import torch
@@ -127,13 +182,8 @@ def main():
     achieved = F * n / (kernel_ms * 1e-3) / 1e12
     log(f"fused kernel {kernel_ms:.4f} ms, {F} flop/nbhd -> {achieved:.2f} TFLOP/s")
 
-    if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 2 x 536870912-byte device copies")
+    if args.calibration:
+        calibration_kernel()
 
     cpu = None
     if not args.no_cpu:
@@ -163,10 +213,98 @@ def main():
                            "HIP graph replay"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": profiled_traffic()},
+        "cpu_baseline": cpu,
+        "detail": {"kernel": "sums_kernel<31,1,2,0,false>", "kernel_ms": kernel_ms,
+                   "flop_per_neighbourhood": F, "loglik": res["loglik"],
+                   "kernel_source_sha256_16": kernel_source_hash()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_2407_02740_amd.autotune as AT
+    from paper_2407_02740_amd import synthetic as S
+    from paper_2407_02740_amd import vecchia as V
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    log("generating 512 uneven datasets")
+    w = S.batched_uneven()
+    ntot = int(w["n"].sum())
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {ntot} observations")
+    start = w["covparms"] * np.array([0.8, 1.3, 1.5])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        vb = V.VecchiaBatch(w["locs"], w["NN"], w["y"], w["X"], w["obs_offset"], w["nn_offset"],
+                            w["n"], w["m"], w["nu"], w["family"], w["nspace"])
+        cp = vb.covparms(start)
+        sched, table = AT.tune_batch(vb, cp, log=log)
+    torch.cuda.synchronize()
+    log(f"schedule: tile {list(sched.tile)}, blocks/CU {list(sched.blocks_per_cu)}")
+    with torch.cuda.stream(stream):
+        vb.fisher_fit(cp, args.warmup, use_graph=True, check=False)
+    torch.cuda.synchronize()
+    vb.check_status("warmup")
+    t1 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        vb.fisher_fit(cp, args.steps, use_graph=True, check=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    vb.check_status("timed steps")
+    elapsed = t2 - t1
+    value = ntot * args.steps / elapsed
+    log(f"{args.steps} steps in {elapsed * 1e3:.2f} ms -> {value:.4e} nbhd/s")
+    # per class: algorithmic flops over the best measured time of its launch
+    classes = {}
+    for c, rows in table.items():
+        sel = [b for b in range(w["nsets"]) if min(k for k, K in enumerate(V.CLASS_K)
+                                                   if w["m"][b] + 1 <= K) == c]
+        flops = sum(int(w["n"][b]) * algorithmic_flops(int(w["m"][b]) + 1, 2, 1, 1) for b in sel)
+        ms = min(r[2] for r in rows)
+        classes[V.CLASS_K[c]] = dict(datasets=len(sel), ms=ms, tflops=flops / (ms * 1e-3) / 1e12)
+    dom = max(classes, key=lambda k: classes[k]["ms"])
+    achieved = classes[dom]["tflops"]
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        oracle.build()
+        threads = min(16, os.cpu_count() or 1)
+        picks = [int(np.flatnonzero(w["m"] == m)[0]) for m in (10, 20, 30, 40)]
+        tc = time.perf_counter()
+        nn = 0
+        for b in picks:
+            d = S.batch_member(w, b)
+            oracle.raw_sums(d["locs"], d["NN"], d["y"], d["X"], d["covparms"], d["family"],
+                            d["nu"], d["nspace"], threads=threads)
+            nn += d["n"]
+        dtc = time.perf_counter() - tc
+        cpu = {"value": nn / dtc, "unit": "neighbourhoods/s", "cores": threads, "kind": "oracle",
+               "sample": f"one dataset of each m in 10/20/30/40 ({nn} neighbourhoods), "
+                         f"{dtc:.2f} s wall"}
+        log(f"CPU oracle {cpu['value']:.4e} nbhd/s")
+    line = {
+        "metric": METRIC_BATCHED, "value": value, "unit": "neighbourhoods/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched_uneven", "datasets": int(w["nsets"]),
+                   "neighbourhoods": ntot, "m": [10, 20, 30, 40], "d": 2, "p": 1,
+                   "covariance": "Matern nu in {0.5, 1.5, 2.5} (sigma2, rho, tau2) per dataset",
+                   "step": "Fisher-scoring iteration of every dataset: persistent class "
+                           "launches + per-dataset reduce + combine + update, HIP graph replay"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": None},
         "cpu_baseline": cpu,
-        "detail": {"kernel": "sums_kernel<31,1,2>", "kernel_ms": kernel_ms,
-                   "flop_per_neighbourhood": F, "loglik": res["loglik"]},
+        "detail": {"dominant_kernel": f"sums_kernel<{dom},1,1,0,true>", "classes": classes,
+                   "schedule": {"tile": list(sched.tile),
+                                "blocks_per_cu": list(sched.blocks_per_cu)}},
     }
     print(json.dumps(line), flush=True)
 

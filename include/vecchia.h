@@ -193,6 +193,112 @@ int vec_fisher_fit(const vec_problem* pb, const double* locs, const int32_t* NNa
                    double max_step, double* raw, double* out, void* workspace,
                    size_t workspace_bytes, int32_t* status, int32_t use_graph, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent datasets
+ * ------------------------------------------------------------------------
+ * Many datasets of uneven n and m, sharing d, p and the covariance family
+ * (smoothness, m and covariance parameters per dataset), are evaluated in
+ * persistent launches fed by a work queue: each dataset is cut into tiles
+ * of consecutive observations, datasets are grouped into size classes by
+ * the neighbourhood size m + 1 <= 11, 21, 31, 41 (one kernel instantiation
+ * per class, VEC_NUM_CLASSES launches at most), and the workgroups of a
+ * class take tiles until its queue is empty.  Every tile owns one row of
+ * partial sums and each dataset's rows are added in a fixed order, so the
+ * results are deterministic and equal to evaluating the datasets one by one
+ * (Algorithm 1 per dataset, Section 3).
+ * Arrays are the concatenation of the datasets' arrays: locs[n_total][d],
+ * y[n_total], X[n_total][p]; NNarray blocks of n rows of m + 1 int32 each,
+ * with indices local to the dataset (0-based, as for a single problem).
+ * Per-dataset arrays: covparms[nsets][P], raw[nsets][nraw],
+ * out[nsets][nout], status[nsets][2] (one status word per dataset, the
+ * observation index in it local to the dataset). */
+
+#define VEC_NUM_CLASSES 4
+
+typedef struct {
+  int32_t nsets;    /* datasets, 1..65535                                  */
+  int32_t d;        /* coordinates per location, 1..4                      */
+  int32_t p;        /* covariates, 1..3                                    */
+  int32_t family;   /* VEC_FAMILY_ISO or VEC_FAMILY_SPACETIME              */
+  int32_t nspace;   /* space-time: leading spatial coordinates, d - 1      */
+  int32_t reserved; /* must be 0                                           */
+  int64_t n_total;  /* rows of the concatenated locs / y / X               */
+  int64_t nn_total; /* int32 entries of the concatenated NNarray blocks    */
+} vec_batch;
+
+typedef struct {
+  int64_t obs_offset; /* first row of the dataset in locs / y / X          */
+  int64_t nn_offset;  /* first entry of its NNarray block                  */
+  int64_t n;          /* observations, 1 <= n < 2^31                       */
+  int32_t m;          /* neighbours, 0..vec_max_m()                        */
+  int32_t reserved;   /* must be 0                                         */
+  double smoothness;  /* 0.5, 1.5 or 2.5                                   */
+} vec_dataset;
+
+/* Per size class: observations per tile (0 = the default, 32) and
+ * persistent workgroups per CU (0 = as many as are resident at once). */
+typedef struct {
+  int32_t tile[VEC_NUM_CLASSES];
+  int32_t blocks_per_cu[VEC_NUM_CLASSES];
+} vec_schedule;
+
+/* Host-side description of a plan, filled by vec_batch_make_plan and passed
+ * unchanged to the calls that use the plan. */
+typedef struct {
+  int32_t nsets;
+  int32_t count[VEC_NUM_CLASSES];   /* datasets per class                 */
+  int32_t grid[VEC_NUM_CLASSES];    /* persistent workgroups per class    */
+  int32_t reserved;
+  int64_t ntiles[VEC_NUM_CLASSES];  /* tiles per class                    */
+  int64_t rows;                     /* partial rows (all tiles)           */
+  int64_t plan_bytes;               /* device bytes the plan occupies     */
+  vec_schedule sched;               /* the schedule, defaults filled in   */
+} vec_batch_plan;
+
+/* Device bytes of the plan of a batch of nsets datasets (0 if invalid). */
+size_t vec_batch_plan_bytes(int32_t nsets);
+
+/* Validate the batch and its HOST array of descriptors sets[nsets], cut the
+ * datasets into tiles and write the device plan to plan_dev (device memory
+ * of at least vec_batch_plan_bytes(nsets) bytes).  The copy is made on
+ * `stream`, which this call synchronises; the plan depends on n, m and the
+ * schedule only, so one plan serves every later evaluation.  Returns
+ * VEC_EINVAL for an invalid batch, descriptor (any offset or size outside
+ * n_total / nn_total) or schedule. */
+int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_schedule* sched,
+                        vec_batch_plan* plan, void* plan_dev, size_t plan_dev_bytes,
+                        void* stream);
+
+/* Device workspace bytes the batched calls need with this plan. */
+size_t vec_batch_workspace_bytes(const vec_batch* bt, const vec_batch_plan* plan);
+
+/* Raw sums of every dataset: raw[nsets][nraw] (layout of vec_raw_sums). */
+int vec_batch_raw_sums(const vec_batch* bt, const vec_batch_plan* plan, const void* plan_dev,
+                       const double* locs, const int32_t* NNarray, const double* y,
+                       const double* X, const double* covparms, double* raw, void* workspace,
+                       size_t workspace_bytes, int32_t* status, void* stream);
+
+/* vec_batch_raw_sums followed by the combine step of every dataset:
+ * out[nsets][nout] (layout of vecchia_loglik_grad_info). */
+int vec_batch_loglik_grad_info(const vec_batch* bt, const vec_batch_plan* plan,
+                               const void* plan_dev, const double* locs, const int32_t* NNarray,
+                               const double* y, const double* X, const double* covparms,
+                               double* raw, double* out, void* workspace, size_t workspace_bytes,
+                               int32_t* status, void* stream);
+
+/* `iters` Fisher-scoring iterations (Eq. 4, as vec_fisher_update) of every
+ * dataset at once; covparms[nsets][P] updated in place on the device, a
+ * dataset whose status holds a flag keeps its parameters.  use_graph and
+ * stream as for vec_fisher_fit. */
+int vec_batch_fisher_fit(const vec_batch* bt, const vec_batch_plan* plan, const void* plan_dev,
+                         const double* locs, const int32_t* NNarray, const double* y,
+                         const double* X, double* covparms, int32_t iters, double max_step,
+                         double* raw, double* out, void* workspace, size_t workspace_bytes,
+                         int32_t* status, int32_t use_graph, void* stream);
+
+/* Reset status[nsets][2] to "no flag" (a kernel). */
+int vec_batch_status_clear(int32_t* status, int32_t nsets, void* stream);
+
 /* Reset status to "no flag" (a kernel, safe inside graph capture). */
 int vec_status_clear(int32_t* status, void* stream);
 

@@ -7,6 +7,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "vecchia.h"
 #include "vecchia_kernels.hpp"
 
@@ -17,7 +19,9 @@ __device__ unsigned long long section_cycles[kSections];
 #endif
 
 // Instantiations live in vecchia_inst_k*.hip (compiled in parallel).
-#define VEC_DECLARE(K, PC, NG, MODE) extern template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE)
+#define VEC_DECLARE(K, PC, NG, MODE, B)                 \
+  extern template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE, B); \
+  extern template VECCHIA_RESIDENT_SIG(K, PC, NG, MODE, B)
 #define VEC_DECLARE_K(K)                   \
   VECCHIA_FOR_MODES(VEC_DECLARE, K, 1);    \
   VECCHIA_FOR_MODES(VEC_DECLARE, K, 2);    \
@@ -25,13 +29,25 @@ __device__ unsigned long long section_cycles[kSections];
 VEC_DECLARE_K(11);
 VEC_DECLARE_K(21);
 VEC_DECLARE_K(31);
+VEC_DECLARE_K(41);
 
-// kLaunch[K index][p - 1][space-time][mode]
-#define VEC_NG(K, PC, NG) \
-  {launch_sums<K, PC, NG, kModeSums>, launch_sums<K, PC, NG, kModeAdjoint>, launch_sums<K, PC, NG, kModeLoglik>}
+// kLaunch[K index][p - 1][space-time][mode]: single problem
+#define VEC_NG(K, PC, NG)                                                                   \
+  {launch_sums<K, PC, NG, kModeSums, false>, launch_sums<K, PC, NG, kModeAdjoint, false>, \
+   launch_sums<K, PC, NG, kModeLoglik, false>}
 #define VEC_PC(K, PC) {VEC_NG(K, PC, 1), VEC_NG(K, PC, 2)}
 #define VEC_ROW(K) {VEC_PC(K, 1), VEC_PC(K, 2), VEC_PC(K, 3)}
-static const launch_fn kLaunch[kNumK][3][2][3] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31)};
+static const launch_fn kLaunch[kNumK][3][2][3] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31),
+                                                   VEC_ROW(41)};
+// kLaunchBatch / kResidentBatch[K index][p - 1][space-time]: batched sums
+#define VEC_BPC(K, PC, F) {F<K, PC, 1, kModeSums, true>, F<K, PC, 2, kModeSums, true>}
+#define VEC_BROW(K, F) {VEC_BPC(K, 1, F), VEC_BPC(K, 2, F), VEC_BPC(K, 3, F)}
+static const launch_fn kLaunchBatch[kNumK][3][2] = {
+    VEC_BROW(11, launch_sums), VEC_BROW(21, launch_sums), VEC_BROW(31, launch_sums),
+    VEC_BROW(41, launch_sums)};
+static const resident_fn kResidentBatch[kNumK][3][2] = {
+    VEC_BROW(11, resident_sums), VEC_BROW(21, resident_sums), VEC_BROW(31, resident_sums),
+    VEC_BROW(41, resident_sums)};
 
 constexpr int kBlocksPerCU = 8;
 constexpr int kMaxP = 3;
@@ -153,9 +169,8 @@ __device__ void small_chol_solve(const double* L, int k, double* x) {
 
 // The "separate function" of Section 3 (profile over beta by generalised
 // least squares).
-__global__ void combine_kernel(int64_t n, int p, int P, const double* __restrict__ raw,
-                               double* __restrict__ out, int32_t* __restrict__ status) {
-  if (threadIdx.x != 0) return;
+__device__ void combine_one(int64_t n, int p, int P, const double* __restrict__ raw,
+                            double* __restrict__ out, int32_t* __restrict__ status) {
   const double logdet = raw[0], ySy = raw[1];
   const double* XSX = raw + 2;
   const double* ySX = XSX + p * p;
@@ -190,11 +205,14 @@ __global__ void combine_kernel(int64_t n, int p, int P, const double* __restrict
   }
 }
 
+__global__ void combine_kernel(int64_t n, int p, int P, const double* __restrict__ raw,
+                               double* __restrict__ out, int32_t* __restrict__ status) {
+  if (threadIdx.x == 0) combine_one(n, p, P, raw, out, status);
+}
+
 // Eq. (4) on the log scale with a step-length cap.
-__global__ void fisher_kernel(int P, int p, const double* __restrict__ out,
-                              double* __restrict__ covparms, int32_t* __restrict__ status,
-                              double max_step) {
-  if (threadIdx.x != 0) return;
+__device__ void fisher_one(int P, const double* __restrict__ out, double* __restrict__ covparms,
+                           int32_t* __restrict__ status, double max_step) {
   if (status[0] != 0) return;
   const double* grad = out + 1;
   const double* info = grad + P;
@@ -215,6 +233,66 @@ __global__ void fisher_kernel(int P, int p, const double* __restrict__ out,
   const double norm = sqrt(norm2);
   const double scale = (norm > max_step) ? max_step / norm : 1.0;
   for (int j = 0; j < P; ++j) covparms[j] = th[j] * exp(g[j] * scale);
+}
+
+__global__ void fisher_kernel(int P, const double* __restrict__ out,
+                              double* __restrict__ covparms, int32_t* __restrict__ status,
+                              double max_step) {
+  if (threadIdx.x == 0) fisher_one(P, out, covparms, status, max_step);
+}
+
+// ----------------------------------------------------------------------------
+// batches of datasets
+// ----------------------------------------------------------------------------
+
+// raw[b][e] = sum of dataset b's partial rows (its tiles, in tile order),
+// one workgroup per (entry, dataset), fixed tree: deterministic.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const int64_t* __restrict__ sets,
+                                                           const double* __restrict__ partials,
+                                                           int nraw, double* __restrict__ raw) {
+  __shared__ double red[256];
+  const int e = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  const int64_t row = sets[b * kSetFields + kSetRow];
+  const int64_t nt = sets[b * kSetFields + kSetTiles];
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < nt; t += 256) s += partials[(row + t) * nraw + e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) raw[b * nraw + e] = red[0];
+}
+
+__global__ void batch_combine_kernel(int nsets, const int64_t* __restrict__ sets, int p, int P,
+                                     int nraw, int nout, const double* __restrict__ raw,
+                                     double* __restrict__ out, int32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nsets)
+    combine_one(sets[(int64_t)b * kSetFields + kSetN], p, P, raw + (int64_t)b * nraw,
+                out + (int64_t)b * nout, status + 2 * b);
+}
+
+__global__ void batch_fisher_kernel(int nsets, int P, int nout, const double* __restrict__ out,
+                                    double* __restrict__ covparms, int32_t* __restrict__ status,
+                                    double max_step) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nsets)
+    fisher_one(P, out + (int64_t)b * nout, covparms + (int64_t)b * P, status + 2 * b, max_step);
+}
+
+__global__ void fill_u32_kernel(unsigned int* __restrict__ x, int count, unsigned int v) {
+  for (int e = threadIdx.x; e < count; e += blockDim.x) x[e] = v;
+}
+
+__global__ void batch_status_clear_kernel(int32_t* status, int nsets) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nsets) {
+    status[2 * b] = 0;
+    status[2 * b + 1] = INT32_MAX;
+  }
 }
 
 // Loglik at the given beta and the scaled gradient from the adjoint sums
@@ -251,9 +329,22 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
   const size_t need = (size_t)grid * nraw_for(dm, mode) * sizeof(double);
   if (!partials || partials_bytes < need) return VEC_EWORKSPACE;
   const int pc = dm.p - 1, ng = (pb->family == VEC_FAMILY_SPACETIME) ? 1 : 0;
-  hipError_t e = kLaunch[dm.kidx][pc][ng][mode](grid, st, pb->m, pb->d, pb->nspace, dm.nu, locs,
-                                                NN, y, X, covparms, beta, i0, i1, partials, status);
-  return hip_code(e);
+  SumsArgs args = {};
+  args.m = pb->m;
+  args.d = pb->d;
+  args.nspace = pb->nspace;
+  args.nu = dm.nu;
+  args.locs = locs;
+  args.NN = NN;
+  args.y = y;
+  args.X = X;
+  args.covparms = covparms;
+  args.beta = beta;
+  args.i0 = i0;
+  args.i1 = i1;
+  args.partials = partials;
+  args.status = status;
+  return hip_code(kLaunch[dm.kidx][pc][ng][mode](grid, st, args));
 }
 
 // Kernel pass over [i0, i1) followed by the fixed-order reduction into raw.
@@ -275,6 +366,110 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(reduce_kernel, dim3(nraw), dim3(256), 0, st, partials, grid, nraw, raw);
   return hip_code(hipGetLastError());
+}
+
+// ----------------------------------------------------------------------------
+// batches of datasets
+// ----------------------------------------------------------------------------
+
+static_assert(VEC_NUM_CLASSES == kNumK, "one size class per kernel size");
+constexpr int kDefaultTile = 32;
+constexpr int kMaxTile = 1 << 20;
+constexpr int kMaxSets = 65535;
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device plan layout: sets[nsets][kSetFields] int64, then per class the
+// tile prefix [nsets + 1] int64, then per class the dataset ids [nsets] int32.
+struct PlanLayout {
+  size_t sets, prefix, ids, bytes;
+};
+static PlanLayout plan_layout(int32_t nsets) {
+  PlanLayout L;
+  L.sets = 0;
+  L.prefix = align256((size_t)nsets * kSetFields * sizeof(int64_t));
+  L.ids = L.prefix + align256((size_t)kNumK * (nsets + 1) * sizeof(int64_t));
+  L.bytes = L.ids + align256((size_t)kNumK * nsets * sizeof(int32_t));
+  return L;
+}
+
+static bool batch_dims(const vec_batch* bt, Dims* dm) {
+  if (!bt || bt->nsets < 1 || bt->nsets > kMaxSets || bt->reserved != 0) return false;
+  if (bt->n_total < 1 || bt->nn_total < 0) return false;
+  vec_problem pb = {};
+  pb.n = 1;
+  pb.m = 0;
+  pb.d = bt->d;
+  pb.p = bt->p;
+  pb.family = bt->family;
+  pb.smoothness = 0.5;
+  pb.nspace = bt->nspace;
+  return dims_of(&pb, dm);
+}
+
+static int nu_code(double smoothness) {
+  if (smoothness == 0.5) return 0;
+  if (smoothness == 1.5) return 1;
+  if (smoothness == 2.5) return 2;
+  return -1;
+}
+
+static size_t batch_ws_bytes(const Dims& dm, const vec_batch_plan* plan) {
+  return align256((size_t)plan->rows * dm.nraw * sizeof(double)) + 256;
+}
+
+static int enqueue_batch_sums(const vec_batch* bt, const Dims& dm, const vec_batch_plan* plan,
+                              const void* plan_dev, const double* locs, const int32_t* NN,
+                              const double* y, const double* X, const double* covparms,
+                              double* raw, void* ws, int32_t* status, hipStream_t st) {
+  const PlanLayout L = plan_layout(plan->nsets);
+  const char* pd = static_cast<const char*>(plan_dev);
+  double* partials = static_cast<double*>(ws);
+  unsigned int* counters = reinterpret_cast<unsigned int*>(
+      static_cast<char*>(ws) + align256((size_t)plan->rows * dm.nraw * sizeof(double)));
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, counters, kNumK, 0u);
+  const int pc = dm.p - 1, ng = (bt->family == VEC_FAMILY_SPACETIME) ? 1 : 0;
+  int64_t row0 = 0;
+  // largest neighbourhoods first
+  for (int c = kNumK - 1; c >= 0; --c) {
+    if (plan->ntiles[c] == 0) continue;
+    SumsArgs args = {};
+    args.d = bt->d;
+    args.nspace = bt->nspace;
+    args.locs = locs;
+    args.NN = NN;
+    args.y = y;
+    args.X = X;
+    args.covparms = covparms;
+    args.partials = partials;
+    args.status = status;
+    args.batch.sets = reinterpret_cast<const int64_t*>(pd + L.sets);
+    args.batch.class_prefix = reinterpret_cast<const int64_t*>(pd + L.prefix) +
+                              (size_t)c * (plan->nsets + 1);
+    args.batch.class_sets = reinterpret_cast<const int32_t*>(pd + L.ids) + (size_t)c * plan->nsets;
+    args.batch.counter = counters + c;
+    args.batch.count = plan->count[c];
+    args.batch.tile = plan->sched.tile[c];
+    // class c's rows follow those of the classes below it
+    row0 = 0;
+    for (int k = 0; k < c; ++k) row0 += plan->ntiles[k];
+    args.batch.row0 = row0;
+    hipError_t e = kLaunchBatch[c][pc][ng](plan->grid[c], st, args);
+    if (e != hipSuccess) return VEC_EHIP;
+  }
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(dm.nraw, plan->nsets), dim3(256), 0, st,
+                     reinterpret_cast<const int64_t*>(pd + L.sets), partials, dm.nraw, raw);
+  return hip_code(hipGetLastError());
+}
+
+static int check_batch_call(const vec_batch* bt, const vec_batch_plan* plan, const void* plan_dev,
+                            const void* locs, const void* NN, const void* y, const void* X,
+                            const void* covparms, const void* raw, void* ws, size_t wsb,
+                            const void* status, Dims* dm) {
+  if (!batch_dims(bt, dm) || !plan || plan->nsets != bt->nsets) return VEC_EINVAL;
+  if (!plan_dev || !locs || !NN || !y || !X || !covparms || !raw || !status) return VEC_EINVAL;
+  if (!ws || wsb < batch_ws_bytes(*dm, plan)) return VEC_EWORKSPACE;
+  return VEC_OK;
 }
 
 }  // namespace vecchia
@@ -399,7 +594,7 @@ int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms
   Dims dm;
   if (!dims_of(pb, &dm) || !out || !covparms || !status || !(max_step > 0.0)) return VEC_EINVAL;
   hipLaunchKernelGGL(fisher_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), dm.P,
-                     dm.p, out, covparms, status, max_step);
+                     out, covparms, status, max_step);
   return hip_code(hipGetLastError());
 }
 
@@ -427,7 +622,7 @@ static int one_iteration(const vec_problem* pb, const Dims& dm, const double* lo
                         wsb, status, st);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, dm.P, raw, out, status);
-  hipLaunchKernelGGL(fisher_kernel, dim3(1), dim3(64), 0, st, dm.P, dm.p, out, covparms, status,
+  hipLaunchKernelGGL(fisher_kernel, dim3(1), dim3(64), 0, st, dm.P, out, covparms, status,
                      max_step);
   return hip_code(hipGetLastError());
 }
@@ -456,16 +651,209 @@ int vec_fisher_fit(const vec_problem* pb, const double* locs, const int32_t* NNa
                          workspace_bytes, status, st);
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc != VEC_OK || e != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return rc != VEC_OK ? rc : VEC_EHIP;
   }
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   if (e == hipSuccess) {
     for (int it = 0; it < iters && e == hipSuccess; ++it) e = hipGraphLaunch(exec, st);
-    hipGraphExecDestroy(exec);
+    (void)hipGraphExecDestroy(exec);
   }
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   return hip_code(e);
+}
+
+size_t vec_batch_plan_bytes(int32_t nsets) {
+  if (nsets < 1 || nsets > kMaxSets) return 0;
+  return plan_layout(nsets).bytes;
+}
+
+int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_schedule* sched,
+                        vec_batch_plan* plan, void* plan_dev, size_t plan_dev_bytes,
+                        void* stream) {
+  Dims dm;
+  if (!batch_dims(bt, &dm) || !sets || !plan || !plan_dev) return VEC_EINVAL;
+  const int32_t ns = bt->nsets;
+  const PlanLayout L = plan_layout(ns);
+  if (plan_dev_bytes < L.bytes) return VEC_EWORKSPACE;
+  vec_batch_plan pl = {};
+  pl.nsets = ns;
+  for (int c = 0; c < kNumK; ++c) {
+    const int t = sched ? sched->tile[c] : 0;
+    const int b = sched ? sched->blocks_per_cu[c] : 0;
+    if (t < 0 || t > kMaxTile || b < 0 || b > 64) return VEC_EINVAL;
+    pl.sched.tile[c] = t ? t : kDefaultTile;
+    pl.sched.blocks_per_cu[c] = b;
+  }
+  // validate every descriptor and find its class
+  std::vector<int> cls(ns);
+  for (int32_t b = 0; b < ns; ++b) {
+    const vec_dataset& s = sets[b];
+    if (s.reserved != 0 || s.n < 1 || s.n >= (int64_t)INT32_MAX) return VEC_EINVAL;
+    if (s.m < 0 || s.m > kKs[kNumK - 1] - 1 || nu_code(s.smoothness) < 0) return VEC_EINVAL;
+    if (s.obs_offset < 0 || s.obs_offset > bt->n_total - s.n) return VEC_EINVAL;
+    const int64_t nn_entries = s.n * (int64_t)(s.m + 1);
+    if (s.nn_offset < 0 || s.nn_offset > bt->nn_total - nn_entries) return VEC_EINVAL;
+    int c = 0;
+    while (s.m + 1 > kKs[c]) ++c;
+    cls[b] = c;
+  }
+  std::vector<int64_t> hsets((size_t)ns * kSetFields);
+  std::vector<int64_t> hprefix((size_t)kNumK * (ns + 1), 0);
+  std::vector<int32_t> hids((size_t)kNumK * ns, 0);
+  int64_t row = 0;
+  for (int c = 0; c < kNumK; ++c) {
+    int32_t cnt = 0;
+    int64_t tiles = 0;
+    int64_t* prefix = hprefix.data() + (size_t)c * (ns + 1);
+    for (int32_t b = 0; b < ns; ++b) {
+      if (cls[b] != c) continue;
+      const vec_dataset& s = sets[b];
+      const int64_t nt = (s.n + pl.sched.tile[c] - 1) / pl.sched.tile[c];
+      int64_t* f = hsets.data() + (size_t)b * kSetFields;
+      f[kSetObs] = s.obs_offset;
+      f[kSetNN] = s.nn_offset;
+      f[kSetN] = s.n;
+      f[kSetM] = s.m;
+      f[kSetNu] = nu_code(s.smoothness);
+      f[kSetClass] = c;
+      f[kSetRow] = row + tiles;
+      f[kSetTiles] = nt;
+      hids[(size_t)c * ns + cnt] = b;
+      prefix[cnt] = tiles;
+      tiles += nt;
+      ++cnt;
+    }
+    prefix[cnt] = tiles;
+    pl.count[c] = cnt;
+    pl.ntiles[c] = tiles;
+    row += tiles;
+  }
+  pl.rows = row;
+  pl.plan_bytes = (int64_t)L.bytes;
+  // persistent grid: resident workgroups per CU (or the schedule's), capped by the tiles
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+  }
+  const int pc = dm.p - 1, ng = (bt->family == VEC_FAMILY_SPACETIME) ? 1 : 0;
+  for (int c = 0; c < kNumK; ++c) {
+    int per_cu = pl.sched.blocks_per_cu[c];
+    if (per_cu == 0) per_cu = kResidentBatch[c][pc][ng]();
+    if (per_cu <= 0) per_cu = 1;
+    const int64_t g = (int64_t)ncu * per_cu;
+    pl.grid[c] = (int32_t)(g < pl.ntiles[c] ? g : pl.ntiles[c]);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* pd = static_cast<char*>(plan_dev);
+  if (hipMemcpyAsync(pd + L.sets, hsets.data(), hsets.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(pd + L.prefix, hprefix.data(), hprefix.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(pd + L.ids, hids.data(), hids.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return VEC_EHIP;
+  *plan = pl;
+  return VEC_OK;
+}
+
+size_t vec_batch_workspace_bytes(const vec_batch* bt, const vec_batch_plan* plan) {
+  Dims dm;
+  if (!batch_dims(bt, &dm) || !plan || plan->nsets != bt->nsets) return 0;
+  return batch_ws_bytes(dm, plan);
+}
+
+int vec_batch_raw_sums(const vec_batch* bt, const vec_batch_plan* plan, const void* plan_dev,
+                       const double* locs, const int32_t* NNarray, const double* y,
+                       const double* X, const double* covparms, double* raw, void* workspace,
+                       size_t workspace_bytes, int32_t* status, void* stream) {
+  Dims dm;
+  int rc = check_batch_call(bt, plan, plan_dev, locs, NNarray, y, X, covparms, raw, workspace,
+                            workspace_bytes, status, &dm);
+  if (rc != VEC_OK) return rc;
+  return enqueue_batch_sums(bt, dm, plan, plan_dev, locs, NNarray, y, X, covparms, raw, workspace,
+                            status, static_cast<hipStream_t>(stream));
+}
+
+static int batch_iteration(const vec_batch* bt, const Dims& dm, const vec_batch_plan* plan,
+                           const void* plan_dev, const double* locs, const int32_t* NN,
+                           const double* y, const double* X, double* covparms, double* raw,
+                           double* out, void* ws, int32_t* status, bool update, double max_step,
+                           hipStream_t st) {
+  int rc = enqueue_batch_sums(bt, dm, plan, plan_dev, locs, NN, y, X, covparms, raw, ws, status, st);
+  if (rc != VEC_OK) return rc;
+  const PlanLayout L = plan_layout(plan->nsets);
+  const int64_t* sets = reinterpret_cast<const int64_t*>(static_cast<const char*>(plan_dev) + L.sets);
+  const int nb = (plan->nsets + 63) / 64;
+  hipLaunchKernelGGL(batch_combine_kernel, dim3(nb), dim3(64), 0, st, plan->nsets, sets, dm.p,
+                     dm.P, dm.nraw, dm.nout, raw, out, status);
+  if (update)
+    hipLaunchKernelGGL(batch_fisher_kernel, dim3(nb), dim3(64), 0, st, plan->nsets, dm.P, dm.nout,
+                       out, covparms, status, max_step);
+  return hip_code(hipGetLastError());
+}
+
+int vec_batch_loglik_grad_info(const vec_batch* bt, const vec_batch_plan* plan,
+                               const void* plan_dev, const double* locs, const int32_t* NNarray,
+                               const double* y, const double* X, const double* covparms,
+                               double* raw, double* out, void* workspace, size_t workspace_bytes,
+                               int32_t* status, void* stream) {
+  Dims dm;
+  int rc = check_batch_call(bt, plan, plan_dev, locs, NNarray, y, X, covparms, raw, workspace,
+                            workspace_bytes, status, &dm);
+  if (rc != VEC_OK) return rc;
+  if (!out) return VEC_EINVAL;
+  return batch_iteration(bt, dm, plan, plan_dev, locs, NNarray, y, X,
+                         const_cast<double*>(covparms), raw, out, workspace, status, false, 1.0,
+                         static_cast<hipStream_t>(stream));
+}
+
+int vec_batch_fisher_fit(const vec_batch* bt, const vec_batch_plan* plan, const void* plan_dev,
+                         const double* locs, const int32_t* NNarray, const double* y,
+                         const double* X, double* covparms, int32_t iters, double max_step,
+                         double* raw, double* out, void* workspace, size_t workspace_bytes,
+                         int32_t* status, int32_t use_graph, void* stream) {
+  Dims dm;
+  int rc = check_batch_call(bt, plan, plan_dev, locs, NNarray, y, X, covparms, raw, workspace,
+                            workspace_bytes, status, &dm);
+  if (rc != VEC_OK) return rc;
+  if (!out || iters < 0 || !(max_step > 0.0)) return VEC_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!use_graph || st == nullptr || iters == 0) {
+    for (int it = 0; it < iters; ++it) {
+      rc = batch_iteration(bt, dm, plan, plan_dev, locs, NNarray, y, X, covparms, raw, out,
+                           workspace, status, true, max_step, st);
+      if (rc != VEC_OK) return rc;
+    }
+    return VEC_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return VEC_EHIP;
+  rc = batch_iteration(bt, dm, plan, plan_dev, locs, NNarray, y, X, covparms, raw, out, workspace,
+                       status, true, max_step, st);
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (rc != VEC_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != VEC_OK ? rc : VEC_EHIP;
+  }
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) {
+    for (int it = 0; it < iters && e == hipSuccess; ++it) e = hipGraphLaunch(exec, st);
+    (void)hipGraphExecDestroy(exec);
+  }
+  (void)hipGraphDestroy(graph);
+  return hip_code(e);
+}
+
+int vec_batch_status_clear(int32_t* status, int32_t nsets, void* stream) {
+  if (!status || nsets < 1 || nsets > kMaxSets) return VEC_EINVAL;
+  hipLaunchKernelGGL(batch_status_clear_kernel, dim3((nsets + 63) / 64), dim3(64), 0,
+                     static_cast<hipStream_t>(stream), status, nsets);
+  return hip_code(hipGetLastError());
 }
 
 #ifdef VECCHIA_SECTION_TIMING

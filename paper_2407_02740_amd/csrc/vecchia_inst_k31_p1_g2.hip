@@ -1,0 +1,11 @@
+// Instantiations of the fused per-neighbourhood kernel for K = 31
+// (m <= 30), p = 1 covariate and space-time ranges: the sums, adjoint and
+// loglik-only modes of the single-problem kernel and the batched sums kernel.
+#include "vecchia_kernels.hpp"
+
+namespace vecchia {
+#define VECCHIA_INSTANTIATE(K, PC, NG, MODE, B) \
+  template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE, B); \
+  template VECCHIA_RESIDENT_SIG(K, PC, NG, MODE, B)
+VECCHIA_FOR_NG(VECCHIA_INSTANTIATE, 31, 1, 2);
+}  // namespace vecchia

@@ -228,12 +228,45 @@ struct CovCoef {
   double ir[2];         // 1/range per group
 };
 
-template <int K, int PC, int NG, int MODE>
-__global__ __launch_bounds__(kThreads) void sums_kernel(
-    const int m, const int d, const int nspace, const int nu, const double* __restrict__ locs,
-    const int32_t* __restrict__ NN, const double* __restrict__ y, const double* __restrict__ X,
-    const double* __restrict__ covparms, const double* __restrict__ beta, const int64_t i0,
-    const int64_t i1, double* __restrict__ partials, int32_t* __restrict__ status) {
+// Batched launches.  The device plan holds, per dataset, kSetFields int64:
+// offset of its rows in locs / y / X, offset of its NNarray block, n, m,
+// smoothness code, size class, first partial row and number of tiles; and
+// per size class the datasets of the class in queue order with the prefix
+// sum of their tiles.  Every tile is a contiguous range of one dataset's
+// observations and owns one row of partial sums, so per-dataset results do
+// not depend on which workgroup took which tile.
+constexpr int kSetFields = 8;
+enum SetField { kSetObs = 0, kSetNN, kSetN, kSetM, kSetNu, kSetClass, kSetRow, kSetTiles };
+
+struct BatchClass {
+  const int64_t* sets;          // [nsets][kSetFields]
+  const int32_t* class_sets;    // datasets of this class, in queue order
+  const int64_t* class_prefix;  // [count + 1]: first tile of each dataset, total last
+  unsigned int* counter;        // work-queue head, zero before the launch
+  int64_t row0;                 // partial row of the class's first tile
+  int32_t count;                // datasets in the class
+  int32_t tile;                 // neighbourhoods per tile
+};
+
+struct SumsArgs {
+  int m, d, nspace, nu;
+  const double* locs;
+  const int32_t* NN;
+  const double* y;
+  const double* X;
+  const double* covparms;  // [P]; batched: [nsets][P]
+  const double* beta;      // adjoint mode: [p]
+  int64_t i0, i1;          // observation range (single problem)
+  double* partials;        // [rows][nraw]
+  int32_t* status;         // [2]; batched: [nsets][2]
+  BatchClass batch;
+};
+
+// BATCH = false: one problem, the grid strides over observations [i0, i1)
+// and each workgroup writes one partial row.  BATCH = true: a persistent
+// grid takes tiles from the class's work queue until it is empty.
+template <int K, int PC, int NG, int MODE, bool BATCH>
+__global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   using G = Geo<K>;
   constexpr int NS = G::NS;
   constexpr int KP = G::KP;
@@ -271,21 +304,35 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   const int grp = threadIdx.x >> 4;
   constexpr double kFar = 1e30;
 
+  // the problem of the current tile (BATCH: one dataset's slice)
+  const int d = a.d;
+  int m = a.m, nu = a.nu;
+  const double* __restrict__ locs = a.locs;
+  const int32_t* __restrict__ NN = a.NN;
+  const double* __restrict__ y = a.y;
+  const double* __restrict__ X = a.X;
+  const double* __restrict__ covparms = a.covparms;
+  int32_t* __restrict__ status = a.status;
+  int64_t i0 = a.i0, total = a.i1 - a.i0;
+
   CovCoef cf;
-  cf.sigma2 = covparms[0];
-  const double tau2 = covparms[P - 1];
-  cf.diag = cf.sigma2 * (1.0 + tau2);
-  cf.ir[0] = 1.0 / covparms[1];
-  cf.ir[1] = (NG == 2) ? 1.0 / covparms[2] : cf.ir[0];
-  cf.c1 = (nu >= 1) ? 1.0 : 0.0;
-  cf.c2 = (nu == 2) ? 1.0 / 3.0 : 0.0;
-  cf.a0 = (nu == 0) ? 0.0 : ((nu == 1) ? 1.0 : 1.0 / 3.0);
-  cf.a1 = (nu == 2) ? 1.0 / 3.0 : 0.0;
-  cf.a2 = (nu == 0) ? 1.0 : 0.0;
-  const double inv_sigma2 = 1.0 / cf.sigma2;
+  double inv_sigma2;
   double bt[PC];
+  auto set_params = [&]() {
+    cf.sigma2 = covparms[0];
+    const double tau2 = covparms[P - 1];
+    cf.diag = cf.sigma2 * (1.0 + tau2);
+    cf.ir[0] = 1.0 / covparms[1];
+    cf.ir[1] = (NG == 2) ? 1.0 / covparms[2] : cf.ir[0];
+    cf.c1 = (nu >= 1) ? 1.0 : 0.0;
+    cf.c2 = (nu == 2) ? 1.0 / 3.0 : 0.0;
+    cf.a0 = (nu == 0) ? 0.0 : ((nu == 1) ? 1.0 : 1.0 / 3.0);
+    cf.a1 = (nu == 2) ? 1.0 / 3.0 : 0.0;
+    cf.a2 = (nu == 0) ? 1.0 : 0.0;
+    inv_sigma2 = 1.0 / cf.sigma2;
 #pragma unroll
-  for (int t = 0; t < PC; ++t) bt[t] = kAdj ? beta[t] : 0.0;
+    for (int t = 0; t < PC; ++t) bt[t] = kAdj ? a.beta[t] : 0.0;
+  };
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
   if (!kLik && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
@@ -299,8 +346,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   }
 
   VEC_TDECL
-  const int64_t total = i1 - i0;
-  const int64_t stride = (int64_t)gridDim.x * kGroupsPerBlock;
+  const int64_t stride = BATCH ? kGroupsPerBlock : (int64_t)gridDim.x * kGroupsPerBlock;
+  const int64_t first = BATCH ? 0 : (int64_t)blockIdx.x * kGroupsPerBlock;
 
   // Neighbour indices of observation ii for this lane's rows: id = -1 for
   // padding rows (and rows >= K), ii for the self row.  Only valid columns
@@ -342,13 +389,67 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
   int64_t idc[NS];
   bool badc = false;
   double zv[NS][4], yv[NS], xv[NS][PC];
-  if ((int64_t)blockIdx.x * kGroupsPerBlock < total) {
-    const int64_t ii = obs_of((int64_t)blockIdx.x * kGroupsPerBlock);
+
+  // sums of the groups (logdet from the running product) into one row of
+  // partials, then the accumulators start again
+  auto flush = [&](double* __restrict__ dst) {
+    __syncthreads();
+    if (threadIdx.x < kGroupsPerBlock) {
+      acc[threadIdx.x][0] = log(vprod[threadIdx.x][0]) + vprod[threadIdx.x][1] * 0.6931471805599453;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRAW; e += kThreads)
+      dst[e] = ((acc[0][e] + acc[1][e]) + acc[2][e]) + acc[3][e];
+    if constexpr (BATCH) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
+      if (threadIdx.x < kGroupsPerBlock) {
+        vprod[threadIdx.x][0] = 1.0;
+        vprod[threadIdx.x][1] = 0.0;
+      }
+      __syncthreads();
+    }
+  };
+  // next tile of the class's work queue (wave-uniform)
+  auto grab = [&]() -> int64_t {
+    unsigned int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(a.batch.counter, 1u);
+    return (int64_t)__builtin_amdgcn_readfirstlane((int)t);
+  };
+
+  int64_t tile = BATCH ? grab() : 0;
+  for (;;) {
+  if constexpr (BATCH) {
+    const BatchClass& bc = a.batch;
+    if (tile >= bc.class_prefix[bc.count]) break;
+    // the dataset of the tile: last k with class_prefix[k] <= tile
+    int lo = 0, hi = bc.count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (bc.class_prefix[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const int ds = bc.class_sets[lo];
+    const int64_t* sd = bc.sets + (int64_t)ds * kSetFields;
+    const int64_t lt = tile - bc.class_prefix[lo];
+    locs = a.locs + sd[kSetObs] * d;
+    y = a.y + sd[kSetObs];
+    X = a.X + sd[kSetObs] * PC;
+    NN = a.NN + sd[kSetNN];
+    m = (int)sd[kSetM];
+    nu = (int)sd[kSetNu];
+    i0 = lt * bc.tile;
+    total = (sd[kSetN] - i0 < bc.tile) ? sd[kSetN] - i0 : bc.tile;
+    covparms = a.covparms + (int64_t)ds * P;
+    status = a.status + 2 * ds;
+  }
+  set_params();
+  if (first < total) {
+    const int64_t ii = obs_of(first);
     fetch_ids(ii, lane, idc, badc);
     fetch_vals(ii, idc, zv, yv, xv);
   }
 
-  for (int64_t base = (int64_t)blockIdx.x * kGroupsPerBlock; base < total; base += stride) {
+  for (int64_t base = first; base < total; base += stride) {
     // an opaque copy of the lane id per iteration keeps the many
     // lane-dependent predicates from being hoisted out of the loop
     int l = lane;
@@ -1002,49 +1103,54 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(
     badc = badn;
     wave_lds_fence();
   }
-  VEC_TFLUSH;
-  __syncthreads();
-  if (threadIdx.x < kGroupsPerBlock) {
-    // logdet of the group: log of the running product of the v's
-    acc[threadIdx.x][0] = log(vprod[threadIdx.x][0]) + vprod[threadIdx.x][1] * 0.6931471805599453;
+  if constexpr (BATCH) {
+    flush(a.partials + (a.batch.row0 + tile) * NRAW);
+    tile = grab();
+  } else {
+    break;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < NRAW; e += kThreads)
-    partials[(size_t)blockIdx.x * NRAW + e] = ((acc[0][e] + acc[1][e]) + acc[2][e]) + acc[3][e];
+  }  // tiles
+  VEC_TFLUSH;
+  if constexpr (!BATCH) flush(a.partials + (int64_t)blockIdx.x * NRAW);
 }
 
 // Host-side launcher of one instantiation.
-template <int K, int PC, int NG, int MODE>
-hipError_t launch_sums(int grid, hipStream_t stream, int m, int d, int nspace, int nu,
-                       const double* locs, const int32_t* NN, const double* y, const double* X,
-                       const double* covparms, const double* beta, int64_t i0, int64_t i1,
-                       double* partials, int32_t* status) {
-  hipLaunchKernelGGL((sums_kernel<K, PC, NG, MODE>), dim3(grid), dim3(kThreads), 0, stream, m, d,
-                     nspace, nu, locs, NN, y, X, covparms, beta, i0, i1, partials, status);
+template <int K, int PC, int NG, int MODE, bool BATCH>
+hipError_t launch_sums(int grid, hipStream_t stream, const SumsArgs& args) {
+  hipLaunchKernelGGL((sums_kernel<K, PC, NG, MODE, BATCH>), dim3(grid), dim3(kThreads), 0, stream,
+                     args);
   return hipGetLastError();
 }
 
-using launch_fn = hipError_t (*)(int, hipStream_t, int, int, int, int, const double*,
-                                 const int32_t*, const double*, const double*, const double*,
-                                 const double*, int64_t, int64_t, double*, int32_t*);
+// Resident workgroups per CU of one instantiation (0 on error).
+template <int K, int PC, int NG, int MODE, bool BATCH>
+int resident_sums() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sums_kernel<K, PC, NG, MODE, BATCH>,
+                                                   kThreads, 0) != hipSuccess)
+    return 0;
+  return nb;
+}
 
-// Explicit instantiation of the launchers of one K and p (both range
-// layouts, all three modes), used by the per-(K, p) translation units.
-#define VECCHIA_LAUNCH_SIG(K, PC, NG, MODE)                                                     \
-  hipError_t launch_sums<K, PC, NG, MODE>(int, hipStream_t, int, int, int, int, const double*,  \
-                                          const int32_t*, const double*, const double*,        \
-                                          const double*, const double*, int64_t, int64_t,      \
-                                          double*, int32_t*)
+using launch_fn = hipError_t (*)(int, hipStream_t, const SumsArgs&);
+using resident_fn = int (*)();
+
+// Explicit instantiation of one K and p: both range layouts, the three
+// modes of the single-problem kernel and the batched sums kernel.
+#define VECCHIA_LAUNCH_SIG(K, PC, NG, MODE, B) \
+  hipError_t launch_sums<K, PC, NG, MODE, B>(int, hipStream_t, const SumsArgs&)
+#define VECCHIA_RESIDENT_SIG(K, PC, NG, MODE, B) int resident_sums<K, PC, NG, MODE, B>()
+#define VECCHIA_FOR_NG(X, K, PC, NG) \
+  X(K, PC, NG, 0, false);            \
+  X(K, PC, NG, 1, false);            \
+  X(K, PC, NG, 2, false);            \
+  X(K, PC, NG, 0, true)
 #define VECCHIA_FOR_MODES(X, K, PC) \
-  X(K, PC, 1, 0);                   \
-  X(K, PC, 2, 0);                   \
-  X(K, PC, 1, 1);                   \
-  X(K, PC, 2, 1);                   \
-  X(K, PC, 1, 2);                   \
-  X(K, PC, 2, 2)
+  VECCHIA_FOR_NG(X, K, PC, 1);      \
+  VECCHIA_FOR_NG(X, K, PC, 2)
 
 // Instantiated K values (K >= m + 1 is padded with identity rows).
-constexpr int kNumK = 3;
-constexpr int kKs[kNumK] = {11, 21, 31};
+constexpr int kNumK = 4;
+constexpr int kKs[kNumK] = {11, 21, 31, 41};
 
 }  // namespace vecchia

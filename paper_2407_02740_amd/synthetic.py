@@ -21,8 +21,13 @@ Workloads (names follow the covariance model of Section 4.3, Eq. 5-6):
   embedded in R^3 on the unit sphere plus time (Section 4.3: satellite data in
   R^3), space-time exponential (1.0, rho_s = chord of 5 deg, rho_t = 3 slices,
   0.1), m = 30, intercept only.
+* ``batched_uneven``  512 independent datasets uniform on [0,1]^2, n uniform
+  in [1000, 50000], m drawn from {10, 20, 30, 40}, Matern with per-dataset
+  log-range ~ U[log 0.02, log 0.3], smoothness from {1/2, 3/2, 5/2} and
+  nugget ratio ~ U[0.01, 0.5], variance 1, intercept only; concatenated
+  arrays with per-dataset offsets.
 
-For the two large workloads the response is a random-Fourier-feature draw of
+For the large workloads the response is a random-Fourier-feature draw of
 the same stationary covariance plus the nugget noise (not a Vecchia draw), so
 that this module stays free of the method's arithmetic.
 """
@@ -30,6 +35,8 @@ that this module stays free of the method's arithmetic.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -273,3 +280,55 @@ def satellite_spacetime(seed: int = 3, slices: int = 64, passes: int = 64, per_p
     y = 0.5 + math.sqrt(covparms[0]) * f + math.sqrt(covparms[0] * covparms[3]) * \
         rng.standard_normal(n)
     return _pack("satellite_spacetime", locs, NN, y, X, covparms, FAMILY_SPACETIME, nu, 3, m)
+
+
+def _one_dataset(args):
+    seed_seq, n_min, n_max, ms, n_features = args
+    rng = np.random.default_rng(seed_seq)
+    n = int(rng.integers(n_min, n_max + 1))
+    m = int(rng.choice(ms))
+    rho = math.exp(rng.uniform(math.log(0.02), math.log(0.3)))
+    nu = float(rng.choice([0.5, 1.5, 2.5]))
+    tau2 = float(rng.uniform(0.01, 0.5))
+    locs = rng.random((n, 2))
+    locs = locs[maxmin_approx(locs, int(rng.integers(1 << 30)))]
+    NN = find_ordered_nn(locs, m, workers=1)
+    f = rff_field(locs / rho, nu, n_features, rng)
+    y = 0.2 + f + math.sqrt(tau2) * rng.standard_normal(n)
+    return locs, NN, y, m, nu, (1.0, rho, tau2)
+
+
+def batched_uneven(seed: int = 4, nsets: int = 512, n_min: int = 1000, n_max: int = 50_000,
+                   ms=(10, 20, 30, 40), n_features: int = 256, workers: int | None = None) -> dict:
+    """Independent 2-D datasets of uneven n and m, concatenated.  Dataset b
+    draws from its own child seed, so the result does not depend on the
+    number of worker processes."""
+    children = np.random.SeedSequence(seed).spawn(nsets)
+    jobs = [(c, n_min, n_max, tuple(ms), n_features) for c in children]
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers > 1 and nsets > 1:
+        with ProcessPoolExecutor(workers) as ex:
+            parts = list(ex.map(_one_dataset, jobs, chunksize=4))
+    else:
+        parts = [_one_dataset(j) for j in jobs]
+    n = np.array([len(p[2]) for p in parts], dtype=np.int64)
+    m = np.array([p[3] for p in parts], dtype=np.int64)
+    obs_offset = np.concatenate([[0], np.cumsum(n)[:-1]])
+    nn_sizes = n * (m + 1)
+    nn_offset = np.concatenate([[0], np.cumsum(nn_sizes)[:-1]])
+    locs = np.concatenate([p[0] for p in parts])
+    NN = np.concatenate([p[1].reshape(-1) for p in parts]).astype(np.int32)
+    y = np.concatenate([p[2] for p in parts])
+    return dict(name="batched_uneven", locs=np.ascontiguousarray(locs), NN=NN, y=y,
+                X=np.ones((len(y), 1)), n=n, m=m, obs_offset=obs_offset, nn_offset=nn_offset,
+                nu=np.array([p[4] for p in parts]), covparms=np.array([p[5] for p in parts]),
+                family=FAMILY_ISO, nspace=0, d=2, p=1, nsets=nsets)
+
+
+def batch_member(w: dict, b: int) -> dict:
+    """Dataset b of a batched workload as a single problem."""
+    a, n, m = int(w["obs_offset"][b]), int(w["n"][b]), int(w["m"][b])
+    o = int(w["nn_offset"][b])
+    NN = w["NN"][o:o + n * (m + 1)].reshape(n, m + 1)
+    return _pack(f"{w['name']}[{b}]", w["locs"][a:a + n], NN, w["y"][a:a + n], w["X"][a:a + n],
+                 tuple(w["covparms"][b]), w["family"], float(w["nu"][b]), w["nspace"], m)

@@ -318,3 +318,202 @@ class VecchiaLoglik(torch.autograd.Function):
 def vecchia_loglik(ev: Vecchia, covparms: torch.Tensor, check: bool = True) -> torch.Tensor:
     """Differentiable profile log-likelihood (see VecchiaLoglik)."""
     return VecchiaLoglik.apply(covparms, ev, check)
+
+
+# ---------------------------------------------------------------------------
+# batches of independent datasets
+# ---------------------------------------------------------------------------
+NUM_CLASSES = 4
+CLASS_K = (11, 21, 31, 41)
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("nsets", ctypes.c_int32), ("d", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("family", ctypes.c_int32), ("nspace", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_total", ctypes.c_int64),
+                ("nn_total", ctypes.c_int64)]
+
+
+class Dataset(ctypes.Structure):
+    _fields_ = [("obs_offset", ctypes.c_int64), ("nn_offset", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("m", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("smoothness", ctypes.c_double)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32 * NUM_CLASSES),
+                ("blocks_per_cu", ctypes.c_int32 * NUM_CLASSES)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("nsets", ctypes.c_int32), ("count", ctypes.c_int32 * NUM_CLASSES),
+                ("grid", ctypes.c_int32 * NUM_CLASSES), ("reserved", ctypes.c_int32),
+                ("ntiles", ctypes.c_int64 * NUM_CLASSES), ("rows", ctypes.c_int64),
+                ("plan_bytes", ctypes.c_int64), ("sched", Schedule)]
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        bp, pl, sc = ctypes.POINTER(Batch), ctypes.POINTER(Plan), ctypes.POINTER(Schedule)
+        L.vec_batch_plan_bytes.restype = ctypes.c_size_t
+        L.vec_batch_plan_bytes.argtypes = [ctypes.c_int32]
+        L.vec_batch_make_plan.restype = ctypes.c_int
+        L.vec_batch_make_plan.argtypes = [bp, ctypes.POINTER(Dataset), sc, pl, _VP,
+                                          ctypes.c_size_t, _VP]
+        L.vec_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.vec_batch_workspace_bytes.argtypes = [bp, pl]
+        L.vec_batch_raw_sums.restype = ctypes.c_int
+        L.vec_batch_raw_sums.argtypes = [bp, pl, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                         ctypes.c_size_t, _VP, _VP]
+        L.vec_batch_loglik_grad_info.restype = ctypes.c_int
+        L.vec_batch_loglik_grad_info.argtypes = [bp, pl, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                                 _VP, ctypes.c_size_t, _VP, _VP]
+        L.vec_batch_fisher_fit.restype = ctypes.c_int
+        L.vec_batch_fisher_fit.argtypes = [bp, pl, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32,
+                                           ctypes.c_double, _VP, _VP, _VP, ctypes.c_size_t, _VP,
+                                           ctypes.c_int32, _VP]
+        L.vec_batch_status_clear.restype = ctypes.c_int
+        L.vec_batch_status_clear.argtypes = [_VP, ctypes.c_int32, _VP]
+        L._batch_ready = True
+    return L
+
+
+def schedule(tile=None, blocks_per_cu=None) -> Schedule:
+    """A schedule from per-class lists (or one value for every class); 0 =
+    the library default."""
+    def four(v):
+        if v is None:
+            return [0] * NUM_CLASSES
+        if isinstance(v, int):
+            return [v] * NUM_CLASSES
+        return list(v)
+    s = Schedule()
+    for c, (t, b) in enumerate(zip(four(tile), four(blocks_per_cu))):
+        s.tile[c] = int(t)
+        s.blocks_per_cu[c] = int(b)
+    return s
+
+
+class VecchiaBatch:
+    """Many independent datasets resident on the device, evaluated together.
+
+    locs, y, X are the concatenation of the datasets' arrays; NN_blocks is a
+    list of per-dataset NNarray blocks (local indices) or their flat
+    concatenation with the offsets in ``nn_offset``."""
+
+    def __init__(self, locs, NN, y, X, obs_offset, nn_offset, n, m, smoothness,
+                 family: int = FAMILY_ISO, nspace: int = 0, device: str = "cuda",
+                 sched: Schedule | None = None):
+        def f64(a):
+            return torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
+
+        self.locs = f64(locs)
+        if self.locs.dim() == 1:
+            self.locs = self.locs[:, None].contiguous()
+        self.NN = torch.as_tensor(NN, dtype=torch.int32).reshape(-1).contiguous().to(device)
+        self.y = f64(y)
+        self.X = f64(X)
+        if self.X.dim() == 1:
+            self.X = self.X[:, None].contiguous()
+        nsets = len(n)
+        self.nsets = nsets
+        self.sets = (Dataset * nsets)()
+        for b in range(nsets):
+            self.sets[b] = Dataset(obs_offset=int(obs_offset[b]), nn_offset=int(nn_offset[b]),
+                                   n=int(n[b]), m=int(m[b]), reserved=0,
+                                   smoothness=float(smoothness[b]))
+        self.n = [int(v) for v in n]
+        self.bt = Batch(nsets=nsets, d=self.locs.shape[1], p=self.X.shape[1], family=family,
+                        nspace=int(nspace), reserved=0, n_total=self.locs.shape[0],
+                        nn_total=self.NN.numel())
+        self.p = self.bt.p
+        pb = Problem(n=1, m=0, d=self.bt.d, p=self.p, family=family, smoothness=0.5,
+                     nspace=int(nspace), reserved=0)
+        L = _batch_lib()
+        self.P = L.vec_nparms(ctypes.byref(pb))
+        if self.P < 0:
+            raise VecchiaError(VEC_EINVAL, "batch description")
+        self.nraw = L.vec_nraw(ctypes.byref(pb))
+        self.nout = L.vec_nout(ctypes.byref(pb))
+        self.device = self.y.device
+        nb = L.vec_batch_plan_bytes(nsets)
+        if nb == 0:
+            raise VecchiaError(VEC_EINVAL, "vec_batch_plan_bytes")
+        self.plan_dev = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        self.status = torch.zeros(nsets, 2, dtype=torch.int32, device=self.device)
+        self.raw = torch.zeros(nsets, self.nraw, dtype=torch.float64, device=self.device)
+        self.out = torch.zeros(nsets, self.nout, dtype=torch.float64, device=self.device)
+        self._ws = None
+        self.make_plan(sched)
+        self.clear_status()
+
+    def make_plan(self, sched: Schedule | None = None):
+        L = _batch_lib()
+        self.plan = Plan()
+        _check(L.vec_batch_make_plan(ctypes.byref(self.bt), self.sets,
+                                     ctypes.byref(sched) if sched is not None else None,
+                                     ctypes.byref(self.plan), self.plan_dev.data_ptr(),
+                                     self.plan_dev.numel() * 8, _stream()), "vec_batch_make_plan")
+        nb = L.vec_batch_workspace_bytes(ctypes.byref(self.bt), ctypes.byref(self.plan))
+        if self._ws is None or self._ws.numel() * 8 < nb:
+            self._ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        return self.plan
+
+    def covparms(self, covparms) -> torch.Tensor:
+        t = torch.as_tensor(covparms, dtype=torch.float64).to(self.device).contiguous()
+        if t.shape != (self.nsets, self.P):
+            raise ValueError(f"covparms must be [{self.nsets}][{self.P}]")
+        return t
+
+    def clear_status(self):
+        _check(_batch_lib().vec_batch_status_clear(self.status.data_ptr(), self.nsets, _stream()),
+               "vec_batch_status_clear")
+
+    def status_codes(self) -> list:
+        host = self.status.cpu().numpy()
+        L = lib()
+        return [L.vec_status_code((ctypes.c_int32 * 2)(int(a), int(b))) for a, b in host]
+
+    def check_status(self, where: str = "device"):
+        host = self.status.cpu().numpy()
+        for b, code in enumerate(self.status_codes()):
+            if code != VEC_OK:
+                raise VecchiaError(code, f"{where}, dataset {b}", int(host[b, 1]))
+
+    def _args(self, cp):
+        return (ctypes.byref(self.bt), ctypes.byref(self.plan), self.plan_dev.data_ptr(),
+                self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(), self.X.data_ptr(),
+                _dev(cp, torch.float64, "covparms"))
+
+    def raw_sums(self, covparms, check: bool = True):
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        _check(_batch_lib().vec_batch_raw_sums(*self._args(cp), self.raw.data_ptr(),
+                                               self._ws.data_ptr(), self._ws.numel() * 8,
+                                               self.status.data_ptr(), _stream()),
+               "vec_batch_raw_sums")
+        if check:
+            self.check_status("vec_batch_raw_sums")
+        return self.raw
+
+    def loglik_grad_info(self, covparms, check: bool = True):
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        _check(_batch_lib().vec_batch_loglik_grad_info(
+            *self._args(cp), self.raw.data_ptr(), self.out.data_ptr(), self._ws.data_ptr(),
+            self._ws.numel() * 8, self.status.data_ptr(), _stream()),
+            "vec_batch_loglik_grad_info")
+        if check:
+            self.check_status("vec_batch_loglik_grad_info")
+        return self.out
+
+    def fisher_fit(self, covparms: torch.Tensor, iters: int, use_graph: bool = True,
+                   max_step: float = 1.0, check: bool = True):
+        _check(_batch_lib().vec_batch_fisher_fit(
+            *self._args(covparms), int(iters), float(max_step), self.raw.data_ptr(),
+            self.out.data_ptr(), self._ws.data_ptr(), self._ws.numel() * 8,
+            self.status.data_ptr(), int(bool(use_graph)), _stream()), "vec_batch_fisher_fit")
+        if check:
+            self.check_status("vec_batch_fisher_fit")
+        return covparms

@@ -76,3 +76,51 @@ def test_status_decoding():
     assert code(2, 5) == V.VEC_EBADNN
     assert code(3, 5) == V.VEC_EBADNN
     assert code(4, 5) == V.VEC_ENONFINITE
+
+
+def test_batch_plan_validation_on_host():
+    """Invalid batches, descriptors and schedules are rejected before any
+    device call (no GPU needed)."""
+    L = V._batch_lib()
+    assert L.vec_batch_plan_bytes(0) == 0 and L.vec_batch_plan_bytes(70000) == 0
+    assert L.vec_batch_plan_bytes(512) > 512 * 8 * 8
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+
+    def plan(bt_kw=None, sets=None, sched=None):
+        bt = V.Batch(nsets=2, d=2, p=1, family=V.FAMILY_ISO, nspace=0, reserved=0, n_total=300,
+                     nn_total=300 * 41)
+        for k, v in (bt_kw or {}).items():
+            setattr(bt, k, v)
+        arr = (V.Dataset * 2)()
+        base = [dict(obs_offset=0, nn_offset=0, n=100, m=10, reserved=0, smoothness=0.5),
+                dict(obs_offset=100, nn_offset=1100, n=200, m=40, reserved=0, smoothness=2.5)]
+        for b in range(2):
+            kw = {**base[b], **((sets or {}).get(b, {}))}
+            arr[b] = V.Dataset(**kw)
+        pl = V.Plan()
+        return L.vec_batch_make_plan(ctypes.byref(bt), arr,
+                                     ctypes.byref(sched) if sched is not None else None,
+                                     ctypes.byref(pl), fake, big, None)
+
+    bad = [
+        dict(bt_kw=dict(nsets=0)), dict(bt_kw=dict(d=5)), dict(bt_kw=dict(p=0)),
+        dict(bt_kw=dict(family=3)), dict(bt_kw=dict(reserved=1)), dict(bt_kw=dict(n_total=299)),
+        dict(bt_kw=dict(nn_total=1100 + 200 * 41 - 1)),
+        dict(sets={0: dict(n=0)}), dict(sets={0: dict(m=-1)}), dict(sets={1: dict(m=41)}),
+        dict(sets={0: dict(smoothness=1.0)}), dict(sets={0: dict(reserved=2)}),
+        dict(sets={1: dict(obs_offset=101)}), dict(sets={0: dict(obs_offset=-1)}),
+        dict(sets={1: dict(nn_offset=300 * 41 - 200 * 41 + 1)}), dict(sets={0: dict(nn_offset=-5)}),
+        dict(sched=V.schedule(tile=-1)), dict(sched=V.schedule(tile=(1 << 21))),
+        dict(sched=V.schedule(blocks_per_cu=-2)),
+    ]
+    for case in bad:
+        assert plan(**case) == V.VEC_EINVAL, case
+    # too small a plan buffer
+    bt = V.Batch(nsets=2, d=2, p=1, family=V.FAMILY_ISO, nspace=0, reserved=0, n_total=300,
+                 nn_total=300 * 41)
+    arr = (V.Dataset * 2)()
+    pl = V.Plan()
+    assert L.vec_batch_make_plan(ctypes.byref(bt), arr, None, ctypes.byref(pl), fake, 16,
+                                 None) == V.VEC_EWORKSPACE
+    assert L.vec_batch_status_clear(None, 2, None) == V.VEC_EINVAL

@@ -95,7 +95,7 @@ def test_satellite_spacetime_reduced():
     run_case(S.satellite_spacetime(slices=4, passes=8, per_pass=131, m=30), tag="satellite 4192")
 
 
-@pytest.mark.parametrize("m", [0, 1, 5, 10, 15, 20, 25, 30])
+@pytest.mark.parametrize("m", [0, 1, 5, 10, 15, 20, 25, 30, 35, 40])
 @pytest.mark.parametrize("family,nu,p", [(V.FAMILY_ISO, 0.5, 1), (V.FAMILY_ISO, 1.5, 3),
                                          (V.FAMILY_ISO, 2.5, 2), (V.FAMILY_SPACETIME, 0.5, 1),
                                          (V.FAMILY_SPACETIME, 2.5, 3)])
