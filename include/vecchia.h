@@ -173,6 +173,20 @@ int vec_loglik_adjoint(const vec_problem* pb, const double* locs, const int32_t*
                        double* dcovparms, void* workspace, size_t workspace_bytes,
                        int32_t* status, void* stream);
 
+/* Kriging weights and conditional variances of observations [i0, i1): the
+ * conditional density of Eq. (3) is N(b' y_s, v) with weights b of the q
+ * neighbours and variance v, which the factor of Algorithm 1 gives (last row
+ * of its inverse).  weights[(i - i0)][0..m-1] receives b in NNarray column
+ * order (0 for the columns beyond q = min(i, m)) and weights[(i - i0)][m]
+ * receives log(v / sigma2), the log conditional variance in correlation
+ * units; row stride m + 1 doubles.  raw receives the sums of vec_loglik over
+ * the range (its first 2 + p*p + p entries).  workspace as for
+ * vec_raw_sums(pb, i0, i1). */
+int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                        const double* y, const double* X, const double* covparms, int64_t i0,
+                        int64_t i1, double* weights, double* raw, void* workspace,
+                        size_t workspace_bytes, int32_t* status, void* stream);
+
 /* One Fisher-scoring step, Eq. (4), on phi = log(covparms):
  * g = covparms .* grad, I = diag(covparms) info diag(covparms),
  * step = I^-1 g scaled to length max_step if longer, covparms *= exp(step).

@@ -34,11 +34,12 @@ VEC_DECLARE_K(41);
 // kLaunch[K index][p - 1][space-time][mode]: single problem
 #define VEC_NG(K, PC, NG)                                                                   \
   {launch_sums<K, PC, NG, kModeSums, false>, launch_sums<K, PC, NG, kModeAdjoint, false>, \
-   launch_sums<K, PC, NG, kModeLoglik, false>}
+   launch_sums<K, PC, NG, kModeLoglik, false>, launch_sums<K, PC, NG, kModeWeights, false>}
 #define VEC_PC(K, PC) {VEC_NG(K, PC, 1), VEC_NG(K, PC, 2)}
 #define VEC_ROW(K) {VEC_PC(K, 1), VEC_PC(K, 2), VEC_PC(K, 3)}
-static const launch_fn kLaunch[kNumK][3][2][3] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31),
-                                                   VEC_ROW(41)};
+constexpr int kNumModes = 4;
+static const launch_fn kLaunch[kNumK][3][2][kNumModes] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31),
+                                                           VEC_ROW(41)};
 // kLaunchBatch / kResidentBatch[K index][p - 1][space-time]: batched sums
 #define VEC_BPC(K, PC, F) {F<K, PC, 1, kModeSums, true>, F<K, PC, 2, kModeSums, true>}
 #define VEC_BROW(K, F) {VEC_BPC(K, 1, F), VEC_BPC(K, 2, F), VEC_BPC(K, 3, F)}
@@ -322,7 +323,7 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
                               const int32_t* NN, const double* y, const double* X,
                               const double* covparms, const double* beta, int64_t i0, int64_t i1,
                               double* partials, size_t partials_bytes, int* grid_out,
-                              int32_t* status, hipStream_t st) {
+                              int32_t* status, hipStream_t st, double* rows_out = nullptr) {
   const int grid = grid_for(i1 - i0);
   *grid_out = grid;
   if (grid == 0) return VEC_OK;
@@ -344,6 +345,7 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
   args.i1 = i1;
   args.partials = partials;
   args.status = status;
+  args.rows_out = rows_out;
   return hip_code(kLaunch[dm.kidx][pc][ng][mode](grid, st, args));
 }
 
@@ -352,7 +354,7 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
                         const int32_t* NN, const double* y, const double* X,
                         const double* covparms, const double* beta, int64_t i0, int64_t i1,
                         double* raw, void* workspace, size_t workspace_bytes, int32_t* status,
-                        hipStream_t st) {
+                        hipStream_t st, double* rows_out = nullptr) {
   const int64_t total = i1 - i0;
   const int nraw = nraw_for(dm, mode);
   if (total == 0) {
@@ -362,7 +364,7 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
   double* partials = static_cast<double*>(workspace);
   int grid = 0;
   int rc = enqueue_block_sums(pb, dm, mode, locs, NN, y, X, covparms, beta, i0, i1, partials,
-                              workspace_bytes, &grid, status, st);
+                              workspace_bytes, &grid, status, st, rows_out);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(reduce_kernel, dim3(nraw), dim3(256), 0, st, partials, grid, nraw, raw);
   return hip_code(hipGetLastError());
@@ -587,6 +589,20 @@ int vec_loglik_adjoint(const vec_problem* pb, const double* locs, const int32_t*
   hipLaunchKernelGGL(adjoint_finalize_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.P, raw,
                      grad_out, loglik, dcovparms, status);
   return hip_code(hipGetLastError());
+}
+
+int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                        const double* y, const double* X, const double* covparms, int64_t i0,
+                        int64_t i1, double* weights, double* raw, void* workspace,
+                        size_t workspace_bytes, int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm)) return VEC_EINVAL;
+  if (i0 < 0 || i1 < i0 || i1 > pb->n) return VEC_EINVAL;
+  if (!locs || !NNarray || !y || !X || !covparms || !weights || !raw || !status)
+    return VEC_EINVAL;
+  return enqueue_sums(pb, dm, kModeWeights, locs, NNarray, y, X, covparms, nullptr, i0, i1, raw,
+                      workspace, workspace_bytes, status, static_cast<hipStream_t>(stream),
+                      weights);
 }
 
 int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms,

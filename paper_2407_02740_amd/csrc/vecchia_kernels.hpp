@@ -106,7 +106,10 @@ constexpr int nraw_of(int p, int P) { return 2 + p * p + p + P * (2 + p * p + p)
 //   kModeAdjoint  the gradient at a given beta by the reverse-mode
 //                 expression (logdet, r'S r, grad[P]; r = y - X beta).
 //   kModeLoglik   the sums of Algorithm 1 alone (logdet, ySy, XSX, ySX).
-constexpr int kModeSums = 0, kModeAdjoint = 1, kModeLoglik = 2;
+//   kModeWeights  the sums of kModeLoglik, and per observation its kriging
+//                 weights b (in NNarray column order) and log(v / sigma2),
+//                 the conditional variance in correlation units.
+constexpr int kModeSums = 0, kModeAdjoint = 1, kModeLoglik = 2, kModeWeights = 3;
 constexpr int nraw_mode(int mode, int p, int P) {
   return mode == kModeSums ? nraw_of(p, P) : (mode == kModeAdjoint ? 2 + P : nraw_of(p, 0));
 }
@@ -259,6 +262,7 @@ struct SumsArgs {
   int64_t i0, i1;          // observation range (single problem)
   double* partials;        // [rows][nraw]
   int32_t* status;         // [2]; batched: [nsets][2]
+  double* rows_out;        // weights mode: [i1 - i0][m + 1]
   BatchClass batch;
 };
 
@@ -276,6 +280,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   constexpr bool kFull = MODE == kModeSums;
   constexpr bool kAdj = MODE == kModeAdjoint;
   constexpr bool kLik = MODE == kModeLoglik;
+  constexpr bool kWts = MODE == kModeWeights;
+  constexpr bool kDeriv = kFull || kAdj;  // derivative work: pair factors and phase 2
   constexpr int NRAW = nraw_mode(MODE, PC, P);
   constexpr int RC = kAdj ? 1 : 1 + PC;  // right-hand sides of the forward substitution
   constexpr int LPN = K * (K - 1) / 2;  // strictly lower L, index r(r-1)/2 + c
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // from which every range derivative of the pair follows (last slot: sink
   // for diagonal entries)
   constexpr int NPAIR = KP * (KP - 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][kLik ? 2 : NPAIR + 2];  // + write sink, + zero
+  __shared__ double sfv[kGroupsPerBlock][kDeriv ? NPAIR + 2 : 2];  // + write sink, + zero
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   };
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
-  if (!kLik && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
+  if (kDeriv && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
   __shared__ double exptab[64];
   static_assert(kThreads == 64, "one table entry per thread");
   exptab[threadIdx.x] = kExp2Tab[threadIdx.x];
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       const double sE1 = cf.sigma2 * ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
       const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
       const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
-      if constexpr (!kLik) {
+      if constexpr (kDeriv) {
         sfv[grp][idx0] = (NG == 1) ? sF0 * h20 * cf.ir[0] : sF0;
         sfv[grp][idx1] = (NG == 1) ? sF1 * h21 * cf.ir[0] : sF1;
       }
@@ -805,11 +811,26 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         fwd_step(x_, rhs);
       });
       // rhs = Lt^{-1} (y, X);  uu = Lt^{-T} e_last (u = uu / sqrt(d_last))
-      sfor<0, NS>([&](auto s_) {
-        constexpr int s = s_.value;
-        rec[grp][row_of(s, l)][RU] = uu[s];  // 0 for rows >= K
-      });
-      wave_lds_fence();
+      if constexpr (kDeriv) {
+        sfor<0, NS>([&](auto s_) {
+          constexpr int s = s_.value;
+          rec[grp][row_of(s, l)][RU] = uu[s];  // 0 for rows >= K
+        });
+        wave_lds_fence();
+      }
+    }
+    if constexpr (kWts) {
+      // uu = (-b, 1): the kriging weights of the neighbours in rows 0..q-1
+      // (NNarray columns 1..q), zero for missing neighbours
+      if (active) {
+        double* __restrict__ wrow = a.rows_out + (i - a.i0) * (int64_t)(m + 1);
+        sfor<0, NS>([&](auto s_) {
+          constexpr int s = s_.value;
+          const int r = row_of(s, l);
+          if (r < m) wrow[r] = (r < q) ? -uu[s] : 0.0;
+          if (r == K - 1) wrow[m] = log(vself * inv_sigma2);
+        });
+      }
     }
 
     if (more) fetch_vals(inext, idn, zv, yv, xv);  // next neighbourhood, in flight until the next gather
@@ -824,7 +845,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // runs interleaved, one step per column.
     double gr[NG][NS];
     double al[NS];
-    if constexpr (!kLik) {
+    if constexpr (kDeriv) {
     int base_a[NS];
     double zrow[NS][4];
     sfor<0, NS>([&](auto s_) {
@@ -901,7 +922,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         gr[1][s_.value] *= cf.ir[1];
       });
     }
-    }  // !kLik
+    }  // kDeriv
 
     if constexpr (kFull) {
     VEC_MARK("w_solve");
@@ -1144,6 +1165,7 @@ using resident_fn = int (*)();
   X(K, PC, NG, 0, false);            \
   X(K, PC, NG, 1, false);            \
   X(K, PC, NG, 2, false);            \
+  X(K, PC, NG, 3, false);            \
   X(K, PC, NG, 0, true)
 #define VECCHIA_FOR_MODES(X, K, PC) \
   VECCHIA_FOR_NG(X, K, PC, 1);      \
