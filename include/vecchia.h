@@ -187,6 +187,25 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
                         int64_t i1, double* weights, double* raw, void* workspace,
                         size_t workspace_bytes, int32_t* status, void* stream);
 
+/* The combine step of vec_loglik on sums assembled by the caller:
+ * raw_sum = raw_a + raw_b (raw_b may be NULL; 2 + p*p + p doubles each,
+ * e.g. the parts of the observations evaluated by two different paths),
+ * then out = [loglik, betahat[p], betainfo[p][p]] over all n
+ * observations. */
+int vec_combine_loglik(const vec_problem* pb, const double* raw_a, const double* raw_b,
+                       double* raw_sum, double* out, int32_t* status, void* stream);
+
+/* The sums of vec_loglik (logdet, ySy, XSX, ySX) over the observations
+ * index[0..count) (device int32, each in [0, n), any order, repeats counted
+ * again) into raw (its first 2 + p*p + p entries).  An entry outside
+ * [0, n) sets VEC_FLAG_BADNN with its position's value ignored.  For
+ * callers that evaluate a subset exactly, e.g. the observations a
+ * surrogate hands back.  workspace as for vec_raw_sums(pb, 0, count). */
+int vec_loglik_sums_at(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                       const double* y, const double* X, const double* covparms,
+                       const int32_t* index, int64_t count, double* raw, void* workspace,
+                       size_t workspace_bytes, int32_t* status, void* stream);
+
 /* One Fisher-scoring step, Eq. (4), on phi = log(covparms):
  * g = covparms .* grad, I = diag(covparms) info diag(covparms),
  * step = I^-1 g scaled to length max_step if longer, covparms *= exp(step).

@@ -15,6 +15,9 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
   at_beta       pinned: central finite differences in theta at a fixed beta
                 away from beta_hat, the dense reverse-mode expression of the
                 gradient, and agreement with combine at beta_hat.
+  kriging_weights pinned: the loglik sums rebuilt from its weights and
+                variances equal raw_sums' (a different code path, C, Neumaier
+                sums); b = 0 and v = 1 + tau2 when the neighbours are far.
   fisher_step   pinned: the Eq. (4) update is a fixed point at the MLE of the
                 AR(1) closed form (scipy optimiser).
 """
@@ -29,6 +32,7 @@ from .oracle import (  # noqa: F401
     cov_matrix,
     fisher_step,
     fit,
+    kriging_weights,
     loglik_grad_info,
     nparms,
     nraw,

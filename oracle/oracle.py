@@ -12,6 +12,9 @@ written from the paper's statement of the method:
                     (generalised least squares, Section 2.1 / Section 3).
 * ``at_beta``    -- the same log-likelihood and theta-gradient at a given
                     (not profiled) mean vector beta.
+* ``kriging_weights`` -- per observation the weights and log conditional
+                    variance of its conditional density (Eq. 3), solved
+                    densely from the definition.
 * ``fisher_step``-- one Fisher-scoring update, Eq. (4), taken on the log scale
                     of the (positive) covariance parameters with a unit cap on
                     the step length.
@@ -220,6 +223,28 @@ def at_beta(raw, n: int, p: int, P: int, beta) -> dict:
         -0.5 * (r["dlogdet"][j] + r["dySy"][j] - 2.0 * beta @ r["dySX"][j]
                 + beta @ r["dXSX"][j] @ beta) for j in range(P)])
     return dict(loglik=loglik, grad=grad)
+
+
+def kriging_weights(locs, NN, covparms, family=FAMILY_ISO, nu=0.5, nspace=0, i0=0, i1=None):
+    """Per observation i in [i0, i1): the weights b = Sigma_s^-1 c of its
+    q = min(i, m) neighbours (NNarray column order, zero beyond q) and
+    log(v / sigma2) with v = Sigma_ii - c^T b, the conditional variance of
+    Eq. (3) in correlation units.  Returns an array [i1 - i0][m + 1]."""
+    NN = np.asarray(NN)
+    n, m1 = NN.shape
+    i1 = n if i1 is None else i1
+    out = np.zeros((i1 - i0, m1))
+    sigma2 = float(covparms[0])
+    for i in range(i0, i1):
+        q = min(i, m1 - 1)
+        idx = list(NN[i, 1:q + 1]) + [i]
+        S, _ = cov_matrix(np.asarray(locs)[idx], covparms, family, nu, nspace)
+        c = S[:q, q]
+        b = np.linalg.solve(S[:q, :q], c) if q else np.zeros(0)
+        v = S[q, q] - c @ b
+        out[i - i0, :q] = b
+        out[i - i0, m1 - 1] = math.log(v / sigma2)
+    return out
 
 
 def loglik_grad_info(locs, NN, y, X, covparms, family=FAMILY_ISO, nu=0.5, nspace=0,

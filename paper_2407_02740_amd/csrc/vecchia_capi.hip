@@ -127,6 +127,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
   if (threadIdx.x == 0) raw[e] = red[0];
 }
 
+// sum[e] = a[e] + b[e] (b may be null)
+__global__ void add_raw_kernel(const double* __restrict__ a, const double* __restrict__ b, int count,
+                               double* __restrict__ sum) {
+  for (int e = threadIdx.x; e < count; e += blockDim.x) sum[e] = b ? a[e] + b[e] : a[e];
+}
+
 __global__ void fill_kernel(double* __restrict__ x, int count, double v) {
   for (int e = threadIdx.x; e < count; e += blockDim.x) x[e] = v;
 }
@@ -323,7 +329,8 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
                               const int32_t* NN, const double* y, const double* X,
                               const double* covparms, const double* beta, int64_t i0, int64_t i1,
                               double* partials, size_t partials_bytes, int* grid_out,
-                              int32_t* status, hipStream_t st, double* rows_out = nullptr) {
+                              int32_t* status, hipStream_t st, double* rows_out = nullptr,
+                              const int32_t* index = nullptr) {
   const int grid = grid_for(i1 - i0);
   *grid_out = grid;
   if (grid == 0) return VEC_OK;
@@ -346,6 +353,8 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
   args.partials = partials;
   args.status = status;
   args.rows_out = rows_out;
+  args.index = index;
+  args.n = pb->n;
   return hip_code(kLaunch[dm.kidx][pc][ng][mode](grid, st, args));
 }
 
@@ -354,7 +363,8 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
                         const int32_t* NN, const double* y, const double* X,
                         const double* covparms, const double* beta, int64_t i0, int64_t i1,
                         double* raw, void* workspace, size_t workspace_bytes, int32_t* status,
-                        hipStream_t st, double* rows_out = nullptr) {
+                        hipStream_t st, double* rows_out = nullptr,
+                        const int32_t* index = nullptr) {
   const int64_t total = i1 - i0;
   const int nraw = nraw_for(dm, mode);
   if (total == 0) {
@@ -364,7 +374,7 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
   double* partials = static_cast<double*>(workspace);
   int grid = 0;
   int rc = enqueue_block_sums(pb, dm, mode, locs, NN, y, X, covparms, beta, i0, i1, partials,
-                              workspace_bytes, &grid, status, st, rows_out);
+                              workspace_bytes, &grid, status, st, rows_out, index);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(reduce_kernel, dim3(nraw), dim3(256), 0, st, partials, grid, nraw, raw);
   return hip_code(hipGetLastError());
@@ -603,6 +613,30 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
   return enqueue_sums(pb, dm, kModeWeights, locs, NNarray, y, X, covparms, nullptr, i0, i1, raw,
                       workspace, workspace_bytes, status, static_cast<hipStream_t>(stream),
                       weights);
+}
+
+int vec_combine_loglik(const vec_problem* pb, const double* raw_a, const double* raw_b,
+                       double* raw_sum, double* out, int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm) || !raw_a || !raw_sum || !out || !status) return VEC_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(add_raw_kernel, dim3(1), dim3(64), 0, st, raw_a, raw_b, nraw_of(dm.p, 0),
+                     raw_sum);
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, 0, raw_sum, out, status);
+  return hip_code(hipGetLastError());
+}
+
+int vec_loglik_sums_at(const vec_problem* pb, const double* locs, const int32_t* NNarray,
+                       const double* y, const double* X, const double* covparms,
+                       const int32_t* index, int64_t count, double* raw, void* workspace,
+                       size_t workspace_bytes, int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm) || count < 0 || count > pb->n) return VEC_EINVAL;
+  if (!locs || !NNarray || !y || !X || !covparms || !raw || !status) return VEC_EINVAL;
+  if (count > 0 && !index) return VEC_EINVAL;
+  return enqueue_sums(pb, dm, kModeLoglik, locs, NNarray, y, X, covparms, nullptr, 0, count, raw,
+                      workspace, workspace_bytes, status, static_cast<hipStream_t>(stream),
+                      nullptr, index);
 }
 
 int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms,

@@ -263,6 +263,8 @@ struct SumsArgs {
   double* partials;        // [rows][nraw]
   int32_t* status;         // [2]; batched: [nsets][2]
   double* rows_out;        // weights mode: [i1 - i0][m + 1]
+  const int32_t* index;    // optional: observations at positions [i0, i1) of this list
+  int64_t n;               // observations of the problem (bounds of index entries)
   BatchClass batch;
 };
 
@@ -385,8 +387,19 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       for (int t = 0; t < PC; ++t) xv[s][t] = X[ids * PC + t];
     });
   };
+  // observation of this group at position bse of the range; with an index
+  // list the positions index it (entries outside [0, n) read observation 0
+  // and are reported as a malformed row by index_bad)
   auto obs_of = [&](int64_t bse) -> int64_t {
-    return i0 + ((bse + grp < total) ? bse + grp : total - 1);
+    const int64_t pos = i0 + ((bse + grp < total) ? bse + grp : total - 1);
+    if (a.index == nullptr) return pos;
+    const int64_t v = a.index[pos];
+    return (v >= 0 && v < a.n) ? v : 0;
+  };
+  auto index_bad = [&](int64_t bse) -> bool {
+    if (a.index == nullptr) return false;
+    const int64_t v = a.index[i0 + ((bse + grp < total) ? bse + grp : total - 1)];
+    return !(v >= 0 && v < a.n);
   };
 
   // Software pipeline over the wave's neighbourhoods: the next NNarray row
@@ -462,6 +475,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     asm volatile("" : "+v"(l));
     const bool active = base + grp < total;
     const int64_t i = obs_of(base);
+    const bool badidx = index_bad(base);
     const int q = (int)(i < (int64_t)m ? i : (int64_t)m);
     const bool more = base + stride < total;
     const int64_t inext = more ? obs_of(base + stride) : i;
@@ -1116,6 +1130,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     }
     }
     VEC_TMARK(11);
+    badnn = badnn || badidx;
     if (active && (badnn || badval)) {
       atomicOr(&status[0], (badnn ? 2 : 0) | (badval ? 4 : 0));
       atomicMin(&status[1], (int32_t)i);

@@ -75,6 +75,9 @@ def lib():
         L.vec_loglik_adjoint.restype = ctypes.c_int
         L.vec_loglik_adjoint.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP, _VP]
+        L.vec_kriging_weights.restype = ctypes.c_int
+        L.vec_kriging_weights.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64,
+                                          ctypes.c_int64, _VP, _VP, _VP, ctypes.c_size_t, _VP, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
         L.vec_fisher_fit.restype = ctypes.c_int
@@ -266,6 +269,29 @@ class Vecchia:
         if check:
             self.check_status("vec_loglik_adjoint")
         return ll, dcp
+
+    def kriging_weights(self, covparms, i0: int = 0, i1: int | None = None,
+                        out: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+        """Per observation of [i0, i1): kriging weights of its neighbours
+        (NNarray column order) and log conditional variance in correlation
+        units, [i1 - i0][m + 1] FP64; self.raw receives the loglik sums."""
+        i1 = self.n if i1 is None else i1
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        m1 = self.pb.m + 1
+        if out is None:
+            out = torch.empty(max(i1 - i0, 0), m1, dtype=torch.float64, device=self.device)
+        if out.shape != (i1 - i0, m1) or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 [i1 - i0][m + 1] tensor")
+        ws = self.workspace(i0, i1)
+        _check(lib().vec_kriging_weights(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), i0, i1, out.data_ptr(),
+            self.raw.data_ptr(), ws.data_ptr(), ws.numel() * 8, self.status.data_ptr(),
+            _stream()), "vec_kriging_weights")
+        if check:
+            self.check_status("vec_kriging_weights")
+        return out
 
     def fisher_update(self, covparms: torch.Tensor, max_step: float = 1.0):
         _check(lib().vec_fisher_update(ctypes.byref(self.pb), self.out.data_ptr(),

@@ -157,6 +157,23 @@ def test_device_errors_are_reported():
     ev.loglik_grad_info(w["covparms"])
 
 
+@pytest.mark.parametrize("m,nu,p", [(0, 0.5, 1), (7, 1.5, 2), (30, 2.5, 1), (40, 0.5, 3)])
+def test_kriging_weights_match_oracle(m, nu, p):
+    w = _random_problem(450, m, V.FAMILY_ISO, nu, p, seed=60 + m)
+    ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], w["family"], w["nu"], 0)
+    for i0, i1 in [(0, 450), (0, 1), (17, 303)]:
+        _say(f"weights m={m} [{i0}, {i1})")
+        got = ev.kriging_weights(w["covparms"], i0, i1).cpu().numpy()
+        ref = oracle.kriging_weights(w["locs"], w["NN"], w["covparms"], w["family"], w["nu"], 0,
+                                     i0, i1)
+        np.testing.assert_allclose(got[:, :m], ref[:, :m], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(got[:, m], ref[:, m], rtol=0, atol=1e-10)
+        raw = ev.raw.cpu().numpy()[:2 + p * p + p]
+        ref_raw = oracle.raw_sums(w["locs"], w["NN"], w["y"], w["X"], w["covparms"], w["family"],
+                                  w["nu"], 0, i0=i0, i1=i1)[:2 + p * p + p]
+        np.testing.assert_allclose(raw, ref_raw, rtol=0, atol=1e-9 * np.abs(ref_raw).max())
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_fisher_fit_matches_oracle(use_graph):
     w = _random_problem(2500, 15, V.FAMILY_ISO, 1.5, 1, seed=11)

@@ -1,0 +1,236 @@
+"""The learned surrogate's kernels against the CPU oracles, through the C ABI.
+
+Network kernels (BF16 operands, FP32 accumulation) against
+oracle/mlp_oracle.py evaluated with the same BF16 rounding points: the two
+differ by FP32-versus-FP64 accumulation and by BF16 roundings that this
+flips, about 2^-9 relative on the few values it touches, so outputs are
+compared at 1e-2 of their scale and gradients blockwise at 2e-2 in norm.
+Everything formed in FP64 (features before their BF16 rounding, surrogate
+sums, hand-back path, combine) is compared at FP64/FP32-input tolerances.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_oracle as MO
+from paper_2407_02740_amd import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2407_02740_amd import surrogate as SG  # noqa: E402
+from paper_2407_02740_amd import vecchia as V  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(MO.NPARAMS)
+    for (wo, bo), (a, b) in zip(MO.OFFSETS, MO.SHAPES):
+        p[wo:wo + a * b] = rng.normal(0, 1.0 / math.sqrt(b), size=a * b)
+        p[bo:bo + a] = rng.normal(0, 0.1, size=a)
+    return p.astype(np.float32).astype(np.float64)
+
+
+def _inputs(rows, seed):
+    rng = np.random.default_rng(seed)
+    x = MO.bf16_round(rng.normal(0, 0.7, size=(rows, MO.IN)))
+    return x, torch.tensor(x, dtype=torch.bfloat16, device="cuda")
+
+
+@pytest.mark.parametrize("rows", [32, 96, 1024])
+def test_mlp_forward_matches_oracle(rows):
+    p = _params(1)
+    x, xd = _inputs(rows, 2)
+    mlp = SG.MLP(params=p)
+    y = mlp.forward(xd).cpu().numpy()
+    ref = MO.forward(p, x, bf16=True)
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 1e-2 * scale, (np.abs(y - ref).max(), scale)
+    # and close to the plain FP64 network: BF16 changes little
+    ref64 = MO.forward(p, x, bf16=False)
+    assert np.abs(y - ref64).max() <= 0.1 * scale
+
+
+@pytest.mark.parametrize("rows", [64, 2048])
+def test_mlp_loss_grad_matches_oracle(rows):
+    p = _params(3)
+    x, xd = _inputs(rows, 4)
+    rng = np.random.default_rng(5)
+    t = rng.normal(0, 0.5, size=(rows, MO.OUT)).astype(np.float32).astype(np.float64)
+    colw = np.ones(MO.OUT)
+    colw[30] = 2.0
+    colw[31] = 0.0
+    mlp = SG.MLP(params=p)
+    loss = mlp.loss_grad(xd, torch.tensor(t, dtype=torch.float32, device="cuda"),
+                         torch.tensor(colw, dtype=torch.float32, device="cuda"), 1.0 / rows)
+    g = mlp.grad.cpu().numpy().astype(np.float64)
+    ref_loss, ref_g = MO.loss_grad(p, x, t, colw, 1.0 / rows, bf16=True)
+    assert abs(float(loss) - ref_loss) <= 1e-2 * ref_loss
+    for L, ((wo, bo), (a, b)) in enumerate(zip(MO.OFFSETS, MO.SHAPES)):
+        for lo, hi, name in ((wo, wo + a * b, "W"), (bo, bo + a, "b")):
+            d = np.linalg.norm(g[lo:hi] - ref_g[lo:hi])
+            assert d <= 2e-2 * np.linalg.norm(ref_g[lo:hi]), (L, name, d,
+                                                              np.linalg.norm(ref_g[lo:hi]))
+
+
+def test_adam_step_matches_its_definition():
+    p = _params(6)
+    mlp = SG.MLP(params=p)
+    rng = np.random.default_rng(7)
+    grads = [rng.normal(0, 1e-2, size=p.size).astype(np.float32) for _ in range(3)]
+    w = p.astype(np.float32).copy()
+    m1 = np.zeros_like(w)
+    m2 = np.zeros_like(w)
+    for k, gk in enumerate(grads, start=1):
+        mlp.grad.copy_(torch.tensor(gk, device="cuda"))
+        mlp.adam(1e-3)
+        m1 = 0.9 * m1 + 0.1 * gk
+        m2 = 0.999 * m2 + 0.001 * gk * gk
+        w = w - 1e-3 * (m1 / (1 - 0.9 ** k)) / (np.sqrt(m2 / (1 - 0.999 ** k)) + 1e-8)
+    got = mlp.p32.cpu().numpy()
+    np.testing.assert_allclose(got, w, rtol=1e-5, atol=1e-7)
+    np.testing.assert_array_equal(mlp.p16.float().cpu().numpy(),
+                                  MO.bf16_round(got).astype(np.float32))
+
+
+def _plane(n, seed, covparms=(1.0, 0.05, 0.05), nu=1.5):
+    w = S.batched_uneven(seed=seed, nsets=1, n_min=n, n_max=n, ms=(30,), workers=1)
+    ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], V.FAMILY_ISO, nu, 0)
+    return w, ev, np.array(covparms)
+
+
+def test_features_match_their_definition():
+    w, ev, cp = _plane(3000, 11)
+    feat, flag = SG.features(ev, cp, 0, 3000, 0.05, 3.0)
+    f = feat.float().cpu().numpy()[:3000]
+    fl = flag.cpu().numpy()[:3000]
+    locs, NN = w["locs"], w["NN"]
+    ir = 1.0 / cp[1]
+    off = (locs[NN[:, 1:].clip(0)] - locs[:, None, :]) * ir          # [n][30][2]
+    off[:30] = 0.0
+    ref = np.zeros((3000, 64))
+    ref[:, :60] = off.astype(np.float32).reshape(3000, 60)
+    ref[:, 60] = 1.5
+    ref[:, 61] = cp[2]
+    np.testing.assert_array_equal(f[30:], MO.bf16_round(ref)[30:].astype(np.float32))
+    length = np.sqrt((off.astype(np.float32) ** 2).sum(-1))
+    want = (np.arange(3000) < 30) | np.any((length < 0.05) | (length > 3.0), axis=1)
+    np.testing.assert_array_equal(fl.astype(bool), want)
+
+
+def test_surrogate_sums_with_exact_weights_equal_the_exact_sums():
+    """Fed the exact weights and variances (rounded to FP32 as the network
+    output is), the surrogate's FP64 sums equal the exact loglik to the
+    FP32 rounding of its inputs; with every observation handed back the
+    result is the exact path's."""
+    w, ev, cp = _plane(20000, 12)
+    W = ev.kriging_weights(cp, 0, ev.n)
+    exact = SG.exact_loglik(ev, cp)
+    mlp = SG.MLP(seed=0, lv_shift=0.0, lv_scale=1.0)
+    sl = SG.SurrogateLoglik(ev, mlp, (0.0, 1e30), chunk=8192)
+    # replace the network by the exact values through the same sums kernel
+    pred = torch.zeros(ev.n, 32, dtype=torch.float32, device="cuda")
+    pred[:, :31] = W.float()
+    flag = torch.zeros(ev.n, dtype=torch.uint8, device="cuda")
+    flag[:30] = 1
+    L = SG._lib()
+    import ctypes
+    sl.nback.zero_()
+    cpd = ev.covparms(cp)
+    rc = L.vec_surrogate_sums(ctypes.byref(ev.pb), ev.NN.data_ptr(), ev.y.data_ptr(),
+                              ev.X.data_ptr(), cpd.data_ptr(), 0, ev.n, pred.data_ptr(),
+                              flag.data_ptr(), 1.0, 0.0, 0.0, sl.raw_s.data_ptr(), 0,
+                              sl.back.data_ptr(), sl.nback.data_ptr(), sl.sws.data_ptr(),
+                              sl.sws.numel(), SG._stream())
+    assert rc == 0
+    assert int(sl.nback.item()) == 30
+    ws = ev.workspace(0, 30)
+    assert L.vec_loglik_sums_at(ctypes.byref(ev.pb), ev.locs.data_ptr(), ev.NN.data_ptr(),
+                                ev.y.data_ptr(), ev.X.data_ptr(), cpd.data_ptr(),
+                                sl.back.data_ptr(), 30, sl.raw_e.data_ptr(), ws.data_ptr(),
+                                ws.numel() * 8, ev.status.data_ptr(), SG._stream()) == 0
+    assert L.vec_combine_loglik(ctypes.byref(ev.pb), sl.raw_s.data_ptr(), sl.raw_e.data_ptr(),
+                                sl.raw_sum.data_ptr(), sl.out.data_ptr(), ev.status.data_ptr(),
+                                SG._stream()) == 0
+    got = float(sl.out[0])
+    assert abs(got - exact["loglik"]) <= 1e-5 * abs(exact["loglik"]), (got, exact)
+    # everything handed back (empty training range): exactly the exact path
+    sl_all = SG.SurrogateLoglik(ev, mlp, (1e30, 0.0), chunk=4096)
+    r = sl_all.evaluate(cp)
+    assert r["handed_back"] == ev.n
+    assert abs(r["loglik"] - exact["loglik"]) <= 1e-12 * abs(exact["loglik"])
+
+
+def test_loglik_sums_at_an_index_list_match_the_oracle():
+    w, ev, cp = _plane(4000, 13, nu=0.5)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(4000, 777, replace=False).astype(np.int32)
+    idx = np.concatenate([idx, idx[:5]])  # repeats count again
+    import ctypes
+    L = SG._lib()
+    raw = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ws = ev.workspace(0, len(idx))
+    idx_d = torch.tensor(idx, device="cuda")
+    cpd = ev.covparms(cp)
+    assert L.vec_loglik_sums_at(ctypes.byref(ev.pb), ev.locs.data_ptr(), ev.NN.data_ptr(),
+                                ev.y.data_ptr(), ev.X.data_ptr(), cpd.data_ptr(),
+                                idx_d.data_ptr(), len(idx), raw.data_ptr(), ws.data_ptr(),
+                                ws.numel() * 8, ev.status.data_ptr(), SG._stream()) == 0
+    ev.check_status("sums_at")
+    ref = np.zeros(4)
+    for i in idx:
+        ref += oracle.raw_sums(w["locs"], w["NN"], w["y"], w["X"], cp, 0, 0.5, 0, i0=int(i),
+                               i1=int(i) + 1)[:4]
+    np.testing.assert_allclose(raw.cpu().numpy(), ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    # an entry outside [0, n) is reported, not read
+    bad = torch.tensor([5, 4000, 7], dtype=torch.int32, device="cuda")
+    ev.clear_status()
+    L.vec_loglik_sums_at(ctypes.byref(ev.pb), ev.locs.data_ptr(), ev.NN.data_ptr(),
+                         ev.y.data_ptr(), ev.X.data_ptr(), cpd.data_ptr(), bad.data_ptr(), 3,
+                         raw.data_ptr(), ws.data_ptr(), ws.numel() * 8, ev.status.data_ptr(),
+                         SG._stream())
+    with pytest.raises(V.VecchiaError) as e:
+        ev.check_status("bad index")
+    assert e.value.code == V.VEC_EBADNN
+
+
+def test_training_learns_and_the_trained_network_gains():
+    """A short training run on neighbourhoods the exact kernel solved lowers
+    the loss, and on a held-out problem the trained network's log-likelihood
+    error is far below an untrained network's and the gradient-free
+    variance-only baseline's."""
+    _say("surrogate: training set")
+    x, raw, dist = SG.training_set(300_000, seed=21, n_min=20_000, n_max=60_000)
+    lv = raw[:, 30]
+    shift, scale = float(lv.mean()), float(lv.std())
+    t = SG.targets_of(raw, shift, scale)
+    mlp = SG.MLP(seed=1, lv_shift=shift, lv_scale=scale)
+    hist = SG.train(mlp, x, t, epochs=3, batch=2048, lr=2e-3, log=_say)
+    assert hist[-1] < 0.5 * hist[0]
+    w, ev, cp = _plane(50_000, 22, covparms=(1.0, 0.1, 0.05), nu=1.5)
+    exact = SG.exact_loglik(ev, cp)
+    gated = SG.SurrogateLoglik(ev, mlp, dist).evaluate(cp)
+    # with the variance gate opened wide every observation with a full
+    # neighbourhood is served, so the errors compare the networks alone
+    trained = SG.SurrogateLoglik(ev, mlp, dist, lv_slack=50.0).evaluate(cp)
+    untrained = SG.SurrogateLoglik(ev, SG.MLP(seed=2, lv_shift=shift, lv_scale=scale), dist,
+                                   lv_slack=50.0).evaluate(cp)
+    n = ev.n
+    err_g = abs(gated["loglik"] - exact["loglik"]) / n
+    err_t = abs(trained["loglik"] - exact["loglik"]) / n
+    err_u = abs(untrained["loglik"] - exact["loglik"]) / n
+    _say(f"surrogate: |dloglik|/n gated {err_g:.3e} (served {gated['served']}), "
+         f"trained {err_t:.3e} (served {trained['served']}), "
+         f"untrained {err_u:.3e} (served {untrained['served']})")
+    assert gated["served"] > 0.5 * n
+    assert err_t < 0.01 * err_u

@@ -374,6 +374,41 @@ def test_reverse_mode_expression_matches_at_beta(family, nu):
     np.testing.assert_allclose(grad, ref["grad"], rtol=1e-10, atol=1e-10 * np.abs(ref["grad"]).max())
 
 
+@pytest.mark.parametrize("nu,p", [(0.5, 1), (2.5, 2)])
+def test_kriging_weights_rebuild_the_loglik_sums(nu, p):
+    """logdet, ySy, XSX and ySX rebuilt from the per-observation weights and
+    conditional variances equal the C oracle's sums."""
+    locs, NN, y, X, cp = _problem(300, 9, p=p, nu=nu, seed=31)
+    W = oracle.kriging_weights(locs, NN, cp, ISO, nu)
+    raw = oracle.unpack_raw(oracle.raw_sums(locs, NN, y, X, cp, ISO, nu), p, 3)
+    logdet = ySy = 0.0
+    XSX = np.zeros((p, p))
+    ySX = np.zeros(p)
+    for i in range(len(y)):
+        q = min(i, 9)
+        s = NN[i, 1:q + 1]
+        b = W[i, :q]
+        v = cp[0] * math.exp(W[i, 9])
+        ey = y[i] - b @ y[s]
+        eX = X[i] - b @ X[s]
+        logdet += math.log(v)
+        ySy += ey * ey / v
+        XSX += np.outer(eX, eX) / v
+        ySX += ey * eX / v
+    assert logdet == pytest.approx(raw["logdet"], rel=1e-12)
+    assert ySy == pytest.approx(raw["ySy"], rel=1e-11)
+    np.testing.assert_allclose(XSX, raw["XSX"], rtol=1e-11)
+    np.testing.assert_allclose(ySX, raw["ySX"], rtol=1e-10, atol=1e-10 * np.abs(ySX).max())
+
+
+def test_kriging_weights_of_far_neighbours_vanish():
+    locs = np.array([[0.0, 0.0], [50.0, 0.0], [0.0, 80.0]])
+    NN = np.array([[0, -1, -1], [1, 0, -1], [2, 0, 1]], dtype=np.int32)
+    W = oracle.kriging_weights(locs, NN, (2.0, 0.1, 0.3), ISO, 0.5)
+    np.testing.assert_allclose(W[:, :2], 0.0, atol=1e-100)
+    np.testing.assert_allclose(W[:, 2], math.log(1.3), rtol=1e-15)
+
+
 def test_fisher_symmetric_positive_semidefinite():
     locs, NN, y, X, cp = _problem(500, 15, d=3, p=2, family=ST, nu=0.5, seed=10)
     info = oracle.loglik_grad_info(locs, NN, y, X, cp, ST, 0.5, nspace=2)["info"]
