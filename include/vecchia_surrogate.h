@@ -94,17 +94,22 @@ size_t vec_surrogate_workspace_bytes(const vec_problem* pb);
  * e_y = y_i - b.y_s and e_X = X_i - b.X_s and the variance is
  * v = sigma2 exp(lv).  An observation is handed back instead (its index
  * appended at back[atomic (*nback)++], order not fixed) if flag marks it,
- * if it has fewer than m neighbours or a malformed NNarray row, or if lv
- * lies outside [log tau2, log(1 + tau2)] widened by lv_slack (no
- * conditional variance of the model lies outside that interval).
+ * if it has fewer than m neighbours or a malformed NNarray row, if lv lies
+ * outside [log tau2, log(1 + tau2)] widened by lv_slack (no conditional
+ * variance of the model lies outside that interval), or if lv < lv_floor.
+ * The floor is the accuracy gate: an error d in the weights changes the
+ * term by about (d' Sigma_s d) / (2 v), so neighbourhoods with a small
+ * conditional variance (strongly correlated, little nugget) need weights
+ * far more accurate than BF16 gives and are better handed back.
  * raw is overwritten (accumulate = 0) or added to (accumulate != 0); the
  * caller zeroes *nback and sizes back for every observation of the calls
  * that share it. */
 int vec_surrogate_sums(const vec_problem* pb, const int32_t* NNarray, const double* y,
                        const double* X, const double* covparms, int64_t i0, int64_t i1,
                        const float* pred, const uint8_t* flag, float lv_scale, float lv_shift,
-                       float lv_slack, double* raw, int32_t accumulate, int32_t* back,
-                       uint32_t* nback, void* workspace, size_t workspace_bytes, void* stream);
+                       float lv_slack, float lv_floor, double* raw, int32_t accumulate,
+                       int32_t* back, uint32_t* nback, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 #ifdef __cplusplus
 }

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void features_kernel(
   out = out || row[0] != (int32_t)i;
   for (int j = 0; j < kM; ++j) {
     float dx = 0.0f, dy = 0.0f;
-    if (j < m && !out) {
+    if (j < m) {
       const int64_t nb = row[1 + j];
       if (nb >= 0 && nb < i) {
         dx = (float)((locs[2 * nb] - xi) * ir);
@@ -234,21 +234,22 @@ __global__ __launch_bounds__(256) void features_kernel(
 // e_y = y_i - b.y_s, e_X = X_i - b.X_s, v = sigma2 exp(lv).  An observation
 // is handed back (its index appended to `back`) if flagged by the feature
 // pass or if lv leaves the range a conditional variance can take,
-// [log tau2, log(1 + tau2)] widened by lv_slack.
+// [log tau2, log(1 + tau2)] widened by lv_slack, or lies below lv_floor.
 template <int PC>
 __global__ __launch_bounds__(256) void sums_kernel(
     int64_t i0, int64_t count, int m, const int32_t* __restrict__ NN, const double* __restrict__ y,
     const double* __restrict__ X, const double* __restrict__ covparms,
     const float* __restrict__ Y, const uint8_t* __restrict__ flag, float lv_scale,
-    float lv_shift, float lv_slack, double* __restrict__ partials, int32_t* __restrict__ back,
-    unsigned int* __restrict__ nback) {
+    float lv_shift, float lv_slack, float lv_floor, double* __restrict__ partials,
+    int32_t* __restrict__ back, unsigned int* __restrict__ nback) {
   constexpr int NR = 2 + PC * PC + PC;
   __shared__ double red[NR][256];
   double acc[NR];
 #pragma unroll
   for (int e = 0; e < NR; ++e) acc[e] = 0.0;
   const double sigma2 = covparms[0], tau2 = covparms[2];
-  const double lv_lo = log(tau2) - lv_slack, lv_hi = log1p(tau2) + lv_slack;
+  const double lv_lo = fmax(log(tau2) - lv_slack, (double)lv_floor);
+  const double lv_hi = log1p(tau2) + lv_slack;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = i0 + t;
@@ -509,8 +510,9 @@ size_t vec_surrogate_workspace_bytes(const vec_problem* pb) {
 int vec_surrogate_sums(const vec_problem* pb, const int32_t* NNarray, const double* y,
                        const double* X, const double* covparms, int64_t i0, int64_t i1,
                        const float* pred, const uint8_t* flag, float lv_scale, float lv_shift,
-                       float lv_slack, double* raw, int32_t accumulate, int32_t* back,
-                       uint32_t* nback, void* workspace, size_t workspace_bytes, void* stream) {
+                       float lv_slack, float lv_floor, double* raw, int32_t accumulate,
+                       int32_t* back, uint32_t* nback, void* workspace, size_t workspace_bytes,
+                       void* stream) {
   if (!pb || pb->family != VEC_FAMILY_ISO || pb->m != kM || pb->p < 1 || pb->p > 3)
     return VEC_EINVAL;
   if (i0 < 0 || i1 < i0 || i1 > pb->n || !NNarray || !y || !X || !covparms || !pred || !raw ||
@@ -526,7 +528,8 @@ int vec_surrogate_sums(const vec_problem* pb, const int32_t* NNarray, const doub
   auto launch = [&](auto pc_) {
     constexpr int PC = decltype(pc_)::value;
     hipLaunchKernelGGL(sums_kernel<PC>, dim3(grid), dim3(256), 0, st, i0, count, pb->m, NNarray,
-                       y, X, covparms, pred, flag, lv_scale, lv_shift, lv_slack, partials, back,
+                       y, X, covparms, pred, flag, lv_scale, lv_shift, lv_slack, lv_floor,
+                       partials, back,
                        reinterpret_cast<unsigned int*>(nback));
   };
   if (pb->p == 1) launch(std::integral_constant<int, 1>{});

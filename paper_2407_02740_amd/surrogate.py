@@ -59,8 +59,8 @@ def _lib():
         L.vec_surrogate_sums.restype = ctypes.c_int
         L.vec_surrogate_sums.argtypes = [pp, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int64,
                                          _VP, _VP, ctypes.c_float, ctypes.c_float,
-                                         ctypes.c_float, _VP, ctypes.c_int32, _VP, _VP, _VP,
-                                         ctypes.c_size_t, _VP]
+                                         ctypes.c_float, ctypes.c_float, _VP, ctypes.c_int32, _VP,
+                                         _VP, _VP, ctypes.c_size_t, _VP]
         L.vec_loglik_sums_at.restype = ctypes.c_int
         L.vec_loglik_sums_at.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP,
                                          _VP, ctypes.c_size_t, _VP, _VP]
@@ -196,8 +196,8 @@ def training_set(n_neigh: int, seed: int = 6, n_min: int = 5_000, n_max: int = 2
         rho = math.exp(rng.uniform(*log_rho))
         nu = float(rng.choice(nus))
         t2 = float(rng.uniform(*tau2))
-        w = S.batched_uneven(seed=int(rng.integers(1 << 30)), nsets=1, n_min=n, n_max=n, ms=(M,),
-                             workers=1)
+        w = S.batch_member(S.batched_uneven(seed=int(rng.integers(1 << 30)), nsets=1, n_min=n,
+                                            n_max=n, ms=(M,), workers=1), 0)
         ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], V.FAMILY_ISO, nu, 0)
         cp = ev.covparms((1.0, rho, t2))
         W = ev.kriging_weights(cp, M, n)
@@ -269,12 +269,13 @@ class SurrogateLoglik:
     network serving the neighbourhoods it can and the exact kernel the rest."""
 
     def __init__(self, ev: V.Vecchia, mlp: MLP, dist_range, chunk: int = 1 << 18,
-                 lv_slack: float = 0.0):
+                 lv_slack: float = 0.0, lv_floor: float = -1e30):
         assert ev.pb.m == M and ev.pb.family == V.FAMILY_ISO and ev.pb.d == 2
         self.ev, self.mlp = ev, mlp
         self.dist_lo, self.dist_hi = dist_range
         self.chunk = _pad32(chunk)
         self.lv_slack = lv_slack
+        self.lv_floor = lv_floor
         dev = ev.device
         L = _lib()
         nr = 2 + ev.p * ev.p + ev.p
@@ -306,7 +307,8 @@ class SurrogateLoglik:
             _check(L.vec_surrogate_sums(ctypes.byref(ev.pb), ev.NN.data_ptr(), ev.y.data_ptr(),
                                         ev.X.data_ptr(), cp.data_ptr(), i0, i1, pred.data_ptr(),
                                         flag.data_ptr(), self.mlp.lv_scale, self.mlp.lv_shift,
-                                        self.lv_slack, self.raw_s.data_ptr(), int(not first),
+                                        self.lv_slack, self.lv_floor, self.raw_s.data_ptr(),
+                                        int(not first),
                                         self.back.data_ptr(), self.nback.data_ptr(),
                                         self.sws.data_ptr(), self.sws.numel(), _stream()),
                    "vec_surrogate_sums")
@@ -347,3 +349,35 @@ def exact_loglik(ev: V.Vecchia, covparms) -> dict:
     o = ev.loglik(covparms).cpu().numpy()
     return dict(loglik=float(o[0]), betahat=o[1:1 + ev.p].copy())
 
+
+
+def validation_loss(mlp: MLP, x: torch.Tensor, t: torch.Tensor, lv_weight: float = 1.0,
+                    batch: int = 8192) -> float:
+    """Mean per-row loss of the network on held-out neighbourhoods."""
+    colw = column_weights(lv_weight, x.device)
+    N = x.shape[0] // batch * batch
+    acc = 0.0
+    for a in range(0, N, batch):
+        acc += float(mlp.loss_grad(x[a:a + batch].contiguous(), t[a:a + batch].contiguous(), colw,
+                                   1.0 / batch))
+    return acc / max(1, N // batch)
+
+
+def calibrate_floor(ev: V.Vecchia, mlp: MLP, dist_range, covparms, bound: float = 1e-6,
+                    floors=None) -> dict:
+    """The lowest variance floor (log v / sigma2) at which the surrogate's
+    |loglik error| / n on the problem `ev` (a validation problem, judged by
+    the exact path) stays within `bound`; returns the floor, the error and
+    the served count at that floor, and the whole sweep."""
+    exact = exact_loglik(ev, covparms)["loglik"]
+    if floors is None:
+        floors = [math.log(v) for v in (0.02, 0.05, 0.1, 0.2, 0.3, 0.5, 0.7, 0.9)] + [1e30]
+    sweep = []
+    chosen = None
+    for f in floors:
+        r = SurrogateLoglik(ev, mlp, dist_range, lv_floor=f).evaluate(covparms)
+        err = abs(r["loglik"] - exact) / ev.n
+        sweep.append(dict(floor=f, err=err, served=r["served"]))
+        if chosen is None and err <= bound:
+            chosen = sweep[-1]
+    return dict(chosen=chosen, sweep=sweep)
