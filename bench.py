@@ -42,6 +42,8 @@ if ROOT not in sys.path:
 
 METRIC = "neighbourhoods/s (loglik+grad+Fisher), n=1M m=30; plain FP64 vs chosen form"
 METRIC_BATCHED = "neighbourhoods/s (loglik+grad+Fisher), 512 uneven datasets, m in {10,20,30,40}"
+METRIC_SURROGATE = "neighbourhoods/s (loglik), surrogate with exact hand-back, n=4M m=30, |dloglik|/n<=1e-6"
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PROFILE = os.path.join(ROOT, "profiles", "sums_kernel_satellite_spacetime_n1M_m30.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02740_amd", "csrc", f)
@@ -113,13 +115,17 @@ def main():
                     help="also run a kernel of known traffic (512 MiB read + 512 MiB write) "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--workload", default="satellite_spacetime",
-                    choices=["satellite_spacetime", "batched_uneven"])
+                    choices=["satellite_spacetime", "batched_uneven", "surrogate_plane"])
+    ap.add_argument("--train-neighbourhoods", type=int, default=10_000_000)
+    ap.add_argument("--epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
         sys.exit(2)
     if args.workload == "batched_uneven":
         return bench_batched(args)
+    if args.workload == "surrogate_plane":
+        return bench_surrogate(args)
 
     import numpy as np
     import torch
@@ -305,6 +311,105 @@ def bench_batched(args):
         "detail": {"dominant_kernel": f"sums_kernel<{dom},1,1,0,true>", "classes": classes,
                    "schedule": {"tile": list(sched.tile),
                                 "blocks_per_cu": list(sched.blocks_per_cu)}},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_surrogate(args):
+    import numpy as np
+    import torch
+
+    from paper_2407_02740_amd import surrogate as SG
+    from paper_2407_02740_amd import synthetic as S
+    from paper_2407_02740_amd import vecchia as V
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    log(f"training set: {args.train_neighbourhoods} neighbourhoods from the exact kernel")
+    x, raw, dist = SG.training_set(args.train_neighbourhoods, seed=6, log=log)
+    lv = raw[:, SG.M]
+    shift, scale = float(lv.mean()), float(lv.std())
+    t = SG.targets_of(raw, shift, scale)
+    del raw
+    log(f"training set ready in {time.perf_counter() - t0:.1f} s: {x.shape[0]} rows, "
+        f"offset lengths [{dist[0]:.4g}, {dist[1]:.4g}]")
+    mlp = SG.MLP(seed=0, lv_shift=shift, lv_scale=scale)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = SG.train(mlp, x, t, epochs=args.epochs, batch=4096, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del x, t
+    log(f"trained {args.epochs} epochs in {train_s:.1f} s, loss {hist[-1]:.4e}")
+    # gate calibrated on a held-out problem of the same shape, then applied
+    cal_w = S.surrogate_plane(seed=55, n=262_144)
+    cal_ev = V.Vecchia(cal_w["locs"], cal_w["NN"], cal_w["y"], cal_w["X"], V.FAMILY_ISO, 1.5, 0)
+    cp = np.array(cal_w["covparms"])
+    cal = SG.calibrate_floor(cal_ev, mlp, dist, cp, bound=1e-6)
+    for row in cal["sweep"]:
+        log(f"calibration floor {row['floor']:.3g}: |dloglik|/n {row['err']:.3e}, served "
+            f"{row['served']} of {cal_ev.n}")
+    floor = cal["chosen"]["floor"]
+    del cal_ev
+    log("generating the evaluation problem (n = 4,194,304, m = 30)")
+    w = S.surrogate_plane()
+    n = w["n"]
+    ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], V.FAMILY_ISO, 1.5, 0)
+    gated = SG.SurrogateLoglik(ev, mlp, dist, lv_floor=floor)
+    served_all = SG.SurrogateLoglik(ev, mlp, dist, lv_slack=50.0)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - a) / reps
+
+    ex, t_exact = timed(lambda: SG.exact_loglik(ev, cp), args.steps)
+    rg, t_gate = timed(lambda: gated.evaluate(cp), args.steps)
+    ra, t_all = timed(lambda: served_all.evaluate(cp), args.steps)
+    err_g = abs(rg["loglik"] - ex["loglik"]) / n
+    err_a = abs(ra["loglik"] - ex["loglik"]) / n
+    log(f"exact {n / t_exact:.4e} nbhd/s; gated {n / t_gate:.4e} nbhd/s, served "
+        f"{rg['served']}, |dloglik|/n {err_g:.3e}; served-all {n / t_all:.4e} nbhd/s, "
+        f"|dloglik|/n {err_a:.3e}")
+    # the network pass alone over one chunk (HIP events on the current stream)
+    rows = served_all.chunk
+    feat, _ = SG.features(ev, cp, 0, rows, 0.0, 1e30)
+    mlp.forward(feat)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        mlp.forward(feat)
+    e1.record()
+    torch.cuda.synchronize()
+    mlp_ms = e0.elapsed_time(e1) / 5
+    macs = 64 * 256 + 2 * 256 * 256 + 256 * 32
+    achieved = 2.0 * macs * rows / (mlp_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC_SURROGATE, "value": n / t_gate, "unit": "neighbourhoods/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * t_gate,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16/f32 network + f64 loglik", "data": "synthetic",
+        "config": {"workload": "surrogate_plane", "n": n, "m": 30, "d": 2, "p": 1,
+                   "covariance": "Matern 3/2 (1.0, 0.05, 0.05)",
+                   "step": "features + network + FP64 sums + exact hand-back + combine",
+                   "training": {"neighbourhoods": int(args.train_neighbourhoods),
+                                "epochs": args.epochs, "seconds": train_s,
+                                "final_loss": hist[-1]}},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_MFMA_TFLOPS,
+                     "traffic": None},
+        "cpu_baseline": None,
+        "detail": {"gate_floor_log_v": floor, "served": rg["served"], "dloglik_per_n": err_g,
+                   "exact_loglik_only_nbhd_per_s": n / t_exact,
+                   "served_all_nbhd_per_s": n / t_all, "served_all_dloglik_per_n": err_a,
+                   "network_kernel_ms_per_chunk": mlp_ms, "chunk_rows": rows,
+                   "calibration": cal["sweep"]},
     }
     print(json.dumps(line), flush=True)
 

@@ -179,41 +179,50 @@ def features(ev: V.Vecchia, covparms, i0: int, i1: int, dist_lo: float, dist_hi:
 
 
 def training_set(n_neigh: int, seed: int = 6, n_min: int = 5_000, n_max: int = 200_000,
-                 log_rho=(math.log(0.02), math.log(0.5)), tau2=(0.01, 0.5),
-                 nus=(0.5, 1.5, 2.5), workers: int | None = None, log=None):
-    """About n_neigh neighbourhoods (observations i >= m of maxmin-ordered
-    uniform 2-D point sets; covariance parameters drawn per set over the
-    ranges of the batched workload, ranges extended down to denser
-    geometries) with inputs and exact targets.  Returns (x BF16 [N][64],
-    raw targets FP64 [N][31] = (b, log v / sigma2), dist range)."""
+                 rho_range=(0.02, 0.5), tau2_range=(0.01, 0.5), nus=(0.5, 1.5, 2.5),
+                 draws_per_set: int = 8, workers: int | None = None, log=None):
+    """About n_neigh neighbourhoods with inputs and exact targets.  Point
+    sets: maxmin-ordered uniform 2-D points (observations i >= m); each set
+    is used with draws_per_set covariance parameter draws (log-uniform range,
+    uniform nugget ratio, smoothness from nus: the batched workload's ranges,
+    the range widened towards denser geometries).  Point sets are drawn on
+    host processes; weights and features come from the library's kernels.
+    Returns (x BF16 [N][64], raw targets FP64 [N][31] = (b, log v / sigma2),
+    range of the neighbour offset lengths)."""
     rng = np.random.default_rng(seed)
+    per_set = draws_per_set * (0.5 * (n_min + n_max) - M)
+    nsets = max(1, int(math.ceil(n_neigh / per_set)))
+    w = S.batched_uneven(seed=int(rng.integers(1 << 30)), nsets=nsets, n_min=n_min, n_max=n_max,
+                         ms=(M,), workers=workers)
     xs, ts = [], []
     lo, hi = np.inf, 0.0
     total = 0
-    sets = 0
-    while total < n_neigh:
-        n = int(rng.integers(n_min, n_max + 1))
-        rho = math.exp(rng.uniform(*log_rho))
-        nu = float(rng.choice(nus))
-        t2 = float(rng.uniform(*tau2))
-        w = S.batch_member(S.batched_uneven(seed=int(rng.integers(1 << 30)), nsets=1, n_min=n,
-                                            n_max=n, ms=(M,), workers=1), 0)
-        ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], V.FAMILY_ISO, nu, 0)
-        cp = ev.covparms((1.0, rho, t2))
-        W = ev.kriging_weights(cp, M, n)
-        feat, flag = features(ev, cp, M, n, 0.0, 1e30)
-        keep = n - M
-        xs.append(feat[:keep])
-        ts.append(W)
-        f = feat[:keep, :2 * M].float()
-        d = torch.sqrt(f[:, 0::2] ** 2 + f[:, 1::2] ** 2)
-        lo = min(lo, float(d.min()))
-        hi = max(hi, float(d.max()))
-        total += keep
-        sets += 1
-        if log and sets % 10 == 0:
-            log(f"training set: {sets} point sets, {total} neighbourhoods")
-    ev.check_status("training_set")
+    for b in range(nsets):
+        d = S.batch_member(w, b)
+        for _ in range(draws_per_set):
+            rho = math.exp(rng.uniform(math.log(rho_range[0]), math.log(rho_range[1])))
+            nu = float(rng.choice(nus))
+            t2 = float(rng.uniform(*tau2_range))
+            ev = V.Vecchia(d["locs"], d["NN"], d["y"], d["X"], V.FAMILY_ISO, nu, 0)
+            cp = ev.covparms((1.0, rho, t2))
+            n = ev.n
+            W = ev.kriging_weights(cp, M, n)
+            feat, _ = features(ev, cp, M, n, 0.0, 1e30)
+            keep = n - M
+            xs.append(feat[:keep])
+            ts.append(W)
+            f = feat[:keep, :2 * M].float()
+            dist = torch.sqrt(f[:, 0::2] ** 2 + f[:, 1::2] ** 2)
+            lo = min(lo, float(dist.min()))
+            hi = max(hi, float(dist.max()))
+            total += keep
+            ev.check_status("training_set")
+            if total >= n_neigh:
+                break
+        if log:
+            log(f"training set: {b + 1} of {nsets} point sets, {total} neighbourhoods")
+        if total >= n_neigh:
+            break
     return torch.cat(xs), torch.cat(ts), (lo, hi)
 
 

@@ -21,6 +21,8 @@ Workloads (names follow the covariance model of Section 4.3, Eq. 5-6):
   embedded in R^3 on the unit sphere plus time (Section 4.3: satellite data in
   R^3), space-time exponential (1.0, rho_s = chord of 5 deg, rho_t = 3 slices,
   0.1), m = 30, intercept only.
+* ``surrogate_plane``  n = 4,194,304 uniform on [0,1]^2, approximate maxmin
+  ordering, m = 30, Matern 3/2 (1.0, 0.05, 0.05), intercept only.
 * ``batched_uneven``  512 independent datasets uniform on [0,1]^2, n uniform
   in [1000, 50000], m drawn from {10, 20, 30, 40}, Matern with per-dataset
   log-range ~ U[log 0.02, log 0.3], smoothness from {1/2, 3/2, 5/2} and
@@ -283,13 +285,13 @@ def satellite_spacetime(seed: int = 3, slices: int = 64, passes: int = 64, per_p
 
 
 def _one_dataset(args):
-    seed_seq, n_min, n_max, ms, n_features = args
+    seed_seq, n_min, n_max, ms, n_features, rho_range, tau2_range = args
     rng = np.random.default_rng(seed_seq)
     n = int(rng.integers(n_min, n_max + 1))
     m = int(rng.choice(ms))
-    rho = math.exp(rng.uniform(math.log(0.02), math.log(0.3)))
+    rho = math.exp(rng.uniform(math.log(rho_range[0]), math.log(rho_range[1])))
     nu = float(rng.choice([0.5, 1.5, 2.5]))
-    tau2 = float(rng.uniform(0.01, 0.5))
+    tau2 = float(rng.uniform(*tau2_range))
     locs = rng.random((n, 2))
     locs = locs[maxmin_approx(locs, int(rng.integers(1 << 30)))]
     NN = find_ordered_nn(locs, m, workers=1)
@@ -299,12 +301,14 @@ def _one_dataset(args):
 
 
 def batched_uneven(seed: int = 4, nsets: int = 512, n_min: int = 1000, n_max: int = 50_000,
-                   ms=(10, 20, 30, 40), n_features: int = 256, workers: int | None = None) -> dict:
+                   ms=(10, 20, 30, 40), n_features: int = 256, workers: int | None = None,
+                   rho_range=(0.02, 0.3), tau2_range=(0.01, 0.5)) -> dict:
     """Independent 2-D datasets of uneven n and m, concatenated.  Dataset b
     draws from its own child seed, so the result does not depend on the
     number of worker processes."""
     children = np.random.SeedSequence(seed).spawn(nsets)
-    jobs = [(c, n_min, n_max, tuple(ms), n_features) for c in children]
+    jobs = [(c, n_min, n_max, tuple(ms), n_features, tuple(rho_range), tuple(tau2_range))
+            for c in children]
     workers = workers or min(16, os.cpu_count() or 1)
     if workers > 1 and nsets > 1:
         with ProcessPoolExecutor(workers) as ex:
@@ -332,3 +336,20 @@ def batch_member(w: dict, b: int) -> dict:
     NN = w["NN"][o:o + n * (m + 1)].reshape(n, m + 1)
     return _pack(f"{w['name']}[{b}]", w["locs"][a:a + n], NN, w["y"][a:a + n], w["X"][a:a + n],
                  tuple(w["covparms"][b]), w["family"], float(w["nu"][b]), w["nspace"], m)
+
+
+def surrogate_plane(seed: int = 5, n: int = 4_194_304, m: int = 30, n_features: int = 512) -> dict:
+    """The surrogate's evaluation problem: n uniform points on [0,1]^2,
+    approximate maxmin ordering, m = 30, Matern 3/2 (1.0, 0.05, 0.05),
+    intercept only."""
+    rng = np.random.default_rng(seed)
+    locs = rng.random((n, 2))
+    order = maxmin_exact(locs) if n <= 20_000 else maxmin_approx(locs, seed)
+    locs = locs[order]
+    NN = find_ordered_nn(locs, m)
+    covparms = (1.0, 0.05, 0.05)
+    nu = 1.5
+    f = rff_field(locs / covparms[1], nu, n_features, rng)
+    y = 0.3 + math.sqrt(covparms[0]) * f + math.sqrt(covparms[0] * covparms[2]) * \
+        rng.standard_normal(n)
+    return _pack("surrogate_plane", locs, NN, y, np.ones((n, 1)), covparms, FAMILY_ISO, nu, 0, m)
