@@ -19,22 +19,30 @@
 //
 // Steps per neighbourhood (Algorithm 1, with the "remaining operations" of
 // the paper written out in the Cholesky-row form):
-//   gather    locsub/ysub/Xsub: coordinates pre-scaled by 1/rho, to LDS.
+//   gather    locsub/ysub/Xsub of the next neighbourhood, prefetched into
+//             registers during the current one; coordinates pre-scaled by
+//             1/rho into LDS.
 //   phase 1   covariance entries, one pair per lane per step with no idle
 //             lanes: off-diagonal 16x16 blocks directly, and the two
 //             triangular diagonal blocks of a slot pair folded into a
 //             17-step loop (lane l takes row l's entry while u <= l, else
-//             row 31-l's entry at column 32-u).
-//   Cholesky  right-looking in registers; column c broadcast with
-//             row_newbcast from its owner lane.
-//   solves    Liy = L^-1 y, LiX = L^-1 X; L to LDS; u = L^-T e_last.
-//   phase 2   g_rho = (dSigma/drho) u for each range parameter: pairs are
-//             scheduled as a round-robin tournament (each round pairs every
-//             row with a distinct partner), so the scatter g[a] += D u_b,
-//             g[b] += D u_a is conflict-free LDS ds_add_f64 traffic; the
-//             derivative entries are recomputed, never stored.
-//   w         w_rho = L^-1 g_rho, w_tau2 = sigma2 L^-1 u, w_sigma2 =
-//             e_last / sigma2 (dSigma/dsigma2 = Sigma / sigma2).
+//             row 31-l's entry at column 32-u).  Each pair also leaves its
+//             range-derivative factor sigma2 (-f'(h)/h) in LDS.
+//   LDL^T     Sigma = Lt D Lt^T, right-looking in registers, column c's
+//             pivot and entries broadcast with row_newbcast from their
+//             owners; Lt is unit lower triangular, L = Lt D^(1/2).
+//   solves    yt = Lt^-1 y, Xt = Lt^-1 X (forward, broadcasts); Lt to LDS
+//             for the transposed access of ut = Lt^-T e_last (backward,
+//             prefetched three steps ahead, interleaved with the forward
+//             substitution).
+//   phase 2   g_rho = (dSigma/drho) ut row by row: each lane sums over all
+//             columns b of its rows a, the pair factors read from LDS
+//             (static offsets, a zero slot on the diagonal), ut_b and z_b
+//             uniform LDS reads one column ahead; nothing is scattered.
+//   w         wt_rho = Lt^-1 g_rho, wt_tau2 = sigma2 Lt^-1 ut (dSigma/dtau2
+//             = sigma2 I), w_sigma2 = e_last / sigma2 (dSigma/dsigma2 =
+//             Sigma / sigma2); in the Cholesky-row form w_j = L^-1 dSigma_j u
+//             with u = ut / sqrt(d_q), so w_j[l] = wt_j[l] / sqrt(d_l d_q).
 //   sums      with Sy_j = sum_{l<q} w_j[l] Liy[l], SX_j likewise,
 //             G_jk = sum_{l<q} w_j[l] w_k[l] (one DPP all-reduce), the self
 //             row gives
@@ -44,9 +52,12 @@
 //               dXSX_j += -(SX_j LiX_q^T + LiX_q SX_j^T) - w_j[q] LiX_q LiX_q^T,
 //               dySX_j += -Sy_j LiX_q - Liy_q SX_j - w_j[q] Liy_q LiX_q,
 //               ainfo_jk += G_jk + w_j[q] w_k[q] / 2,
-//             accumulated per group in LDS by the self row's lane.
+//             (Liy_q = yt_q / sqrt(d_q), v = d_q) accumulated per group in
+//             LDS by the self row's lane.
 // The per-workgroup sums go to partials[block][nraw]; a second kernel adds
-// them in a fixed order, so results are deterministic.
+// them in a fixed order, so results are deterministic.  Other modes of the
+// same kernel (adjoint, loglik only, kriging weights) and the batched
+// work-queue schedule are described where they branch off below.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -284,6 +295,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   constexpr bool kLik = MODE == kModeLoglik;
   constexpr bool kWts = MODE == kModeWeights;
   constexpr bool kDeriv = kFull || kAdj;  // derivative work: pair factors and phase 2
+  // Above K = 31 the stored pair factors would take the LDS of two more
+  // workgroups per CU: phase 2 recomputes them from the coordinates instead.
+  constexpr bool kRecomp = kDeriv && K > 31;
+  constexpr bool kStoreF = kDeriv && !kRecomp;
   constexpr int NRAW = nraw_mode(MODE, PC, P);
   constexpr int RC = kAdj ? 1 : 1 + PC;  // right-hand sides of the forward substitution
   constexpr int LPN = K * (K - 1) / 2;  // strictly lower L, index r(r-1)/2 + c
@@ -306,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // from which every range derivative of the pair follows (last slot: sink
   // for diagonal entries)
   constexpr int NPAIR = KP * (KP - 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][kDeriv ? NPAIR + 2 : 2];  // + write sink, + zero
+  __shared__ double sfv[kGroupsPerBlock][kStoreF ? NPAIR + 2 : 2];  // + write sink, + zero
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -343,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   };
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
-  if (kDeriv && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
+  if (kStoreF && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
   __shared__ double exptab[64];
   static_assert(kThreads == 64, "one table entry per thread");
   exptab[threadIdx.x] = kExp2Tab[threadIdx.x];
@@ -574,7 +589,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       const double sE1 = cf.sigma2 * ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
       const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
       const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
-      if constexpr (kDeriv) {
+      if constexpr (kStoreF) {
         sfv[grp][idx0] = (NG == 1) ? sF0 * h20 * cf.ir[0] : sF0;
         sfv[grp][idx1] = (NG == 1) ? sF1 * h21 * cf.ir[0] : sF1;
       }
@@ -866,7 +881,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int s = s_.value;
       const int a = row_of(s, l);
       base_a[s] = a * (a - 1) / 2;
-      if constexpr (NG == 2) {
+      if constexpr (NG == 2 || kRecomp) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) zrow[s][k] = rec[grp][a][RZ + k];
       }
@@ -877,11 +892,11 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int b = decltype(b_)::value;
       constexpr int CB = b * (b - 1) / 2;
       ub = rec[grp][b][RU];
-      if constexpr (NG == 2) {
+      if constexpr (NG == 2 || kRecomp) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) zb[k] = rec[grp][b][RZ + k];
       }
-      sfor<0, NS>([&](auto s_) {
+      if constexpr (!kRecomp) sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
         const int a = row_of(s, l);
         int idx;
@@ -910,6 +925,35 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         for (int k = 0; k < 4; ++k) zb[k] = zbn[k];
         sfor<0, NS>([&](auto s_) { Sv[s_.value] = Svn[s_.value]; });
         if constexpr (b + 1 < K) col_load(std::integral_constant<int, b + 1>{}, ubn, zbn, Svn);
+        if constexpr (kRecomp) {
+          // sigma2 (-f'(h)/h) of the pair (a, b) again, as in phase 1 (the
+          // diagonal has h2 = 0 and padding rows exp(-h) = 0: both add 0)
+          sfor<0, NS>([&](auto s_) {
+            constexpr int s = s_.value;
+            double h2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const double dz = zrow[s][k] - zb[k];
+              h2 = __builtin_fma(dz, dz, h2);
+            }
+            double hh, hi;
+            dist_from_sq(h2, hh, hi);
+            const double x = fmax(-hh, -800.0);
+            const double nn = rint(x * kInvLn2x64);
+            const int in = (int)nn;
+            const double T = exptab[in & 63];
+            double r = __builtin_fma(-nn, kLn2d64Hi, x);
+            r = __builtin_fma(-nn, kLn2d64Lo, r);
+            double qq = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+            qq = __builtin_fma(qq, r, 1.0 / 6.0);
+            qq = __builtin_fma(qq, r, 0.5);
+            qq = __builtin_fma(qq, r, 1.0);
+            qq *= r;
+            const double sE = cf.sigma2 * ldexp(__builtin_fma(T, qq, T), in >> 6);
+            const double sF = sE * __builtin_fma(cf.a1, hh, __builtin_fma(cf.a2, hi, cf.a0));
+            Sv[s] = (NG == 1) ? sF * h2 * cf.ir[0] : sF;
+          });
+        }
         sfor<0, NS>([&](auto s_) {
           constexpr int s = s_.value;
           if constexpr (NG == 1) {
