@@ -353,7 +353,7 @@ def bench_surrogate(args):
     floor = cal["chosen"]["floor"]
     del cal_ev
     log("generating the evaluation problem (n = 4,194,304, m = 30)")
-    w = S.surrogate_plane()
+    w = S.surrogate_plane(log=log)
     n = w["n"]
     ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], V.FAMILY_ISO, 1.5, 0)
     gated = SG.SurrogateLoglik(ev, mlp, dist, lv_floor=floor)
@@ -390,6 +390,20 @@ def bench_surrogate(args):
     mlp_ms = e0.elapsed_time(e1) / 5
     macs = 64 * 256 + 2 * 256 * 256 + 256 * 32
     achieved = 2.0 * macs * rows / (mlp_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        oracle.build()
+        threads = min(16, os.cpu_count() or 1)
+        S_ = min(args.cpu_sample, n)
+        tc = time.perf_counter()
+        oracle.raw_sums(w["locs"], w["NN"], w["y"], w["X"], w["covparms"], w["family"], w["nu"],
+                        w["nspace"], i0=n - S_, i1=n, threads=threads)
+        dtc = time.perf_counter() - tc
+        cpu = {"value": S_ / dtc, "unit": "neighbourhoods/s", "cores": threads, "kind": "oracle",
+               "sample": f"last {S_} of {n} neighbourhoods (loglik, gradient and Fisher sums), "
+                         f"{dtc:.2f} s wall"}
     line = {
         "metric": METRIC_SURROGATE, "value": n / t_gate, "unit": "neighbourhoods/s",
         "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * t_gate,
@@ -404,7 +418,7 @@ def bench_surrogate(args):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_MFMA_TFLOPS,
                      "traffic": None},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
         "detail": {"gate_floor_log_v": floor, "served": rg["served"], "dloglik_per_n": err_g,
                    "exact_loglik_only_nbhd_per_s": n / t_exact,
                    "served_all_nbhd_per_s": n / t_all, "served_all_dloglik_per_n": err_a,

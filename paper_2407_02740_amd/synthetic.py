@@ -109,7 +109,7 @@ def maxmin_approx(locs: np.ndarray, seed: int = 0) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # nearest previously ordered neighbours
 # ----------------------------------------------------------------------------
-def find_ordered_nn(locs: np.ndarray, m: int, workers: int = -1) -> np.ndarray:
+def find_ordered_nn(locs: np.ndarray, m: int, workers: int = -1, log=None) -> np.ndarray:
     """NNarray[n][m+1] (int32, 0-based): row i = [i, its min(i, m) nearest
     neighbours among observations 0..i-1 by increasing distance, -1 ...]."""
     from scipy.spatial import cKDTree
@@ -153,6 +153,8 @@ def find_ordered_nn(locs: np.ndarray, m: int, workers: int = -1) -> np.ndarray:
             if k >= b1:
                 break
             k = min(b1, 2 * k)
+        if log:
+            log(f"neighbours of observations [{b0}, {b1}) found")
         b0 = b1
     return NN
 
@@ -338,7 +340,8 @@ def batch_member(w: dict, b: int) -> dict:
                  tuple(w["covparms"][b]), w["family"], float(w["nu"][b]), w["nspace"], m)
 
 
-def surrogate_plane(seed: int = 5, n: int = 4_194_304, m: int = 30, n_features: int = 512) -> dict:
+def surrogate_plane(seed: int = 5, n: int = 4_194_304, m: int = 30, n_features: int = 512,
+                    log=None) -> dict:
     """The surrogate's evaluation problem: n uniform points on [0,1]^2,
     approximate maxmin ordering, m = 30, Matern 3/2 (1.0, 0.05, 0.05),
     intercept only."""
@@ -346,7 +349,7 @@ def surrogate_plane(seed: int = 5, n: int = 4_194_304, m: int = 30, n_features: 
     locs = rng.random((n, 2))
     order = maxmin_exact(locs) if n <= 20_000 else maxmin_approx(locs, seed)
     locs = locs[order]
-    NN = find_ordered_nn(locs, m)
+    NN = find_ordered_nn(locs, m, log=log)
     covparms = (1.0, 0.05, 0.05)
     nu = 1.5
     f = rff_field(locs / covparms[1], nu, n_features, rng)
