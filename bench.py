@@ -115,7 +115,8 @@ def main():
                     help="also run a kernel of known traffic (512 MiB read + 512 MiB write) "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--workload", default="satellite_spacetime",
-                    choices=["satellite_spacetime", "batched_uneven", "surrogate_plane"])
+                    choices=["satellite_spacetime", "batched_uneven", "surrogate_plane",
+                             "sweep"])
     ap.add_argument("--train-neighbourhoods", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=2)
     args = ap.parse_args()
@@ -126,6 +127,8 @@ def main():
         return bench_batched(args)
     if args.workload == "surrogate_plane":
         return bench_surrogate(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import numpy as np
     import torch
@@ -425,6 +428,63 @@ def bench_surrogate(args):
                    "network_kernel_ms_per_chunk": mlp_ms, "chunk_rows": rows,
                    "calibration": cal["sweep"]},
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sweep(args):
+    """Throughput over problem sizes and neighbour counts (2-D Matern 3/2,
+    loglik + gradient + Fisher): kernel-only time (HIP events, median of the
+    repetitions) and end-to-end time from host arrays (host-to-device copies,
+    evaluation, result back on the host)."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from paper_2407_02740_amd import synthetic as S
+    from paper_2407_02740_amd import vecchia as V
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    rows = []
+    for n in (1 << 15, 1 << 17, 1 << 19):
+        base = S.surrogate_plane(seed=7, n=n, m=40, log=None)
+        for m in (10, 30, 40):
+            NN = np.ascontiguousarray(base["NN"][:, :m + 1])
+            cp = np.array(base["covparms"])
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                ev = V.Vecchia(base["locs"], NN, base["y"], base["X"], V.FAMILY_ISO, 1.5, 0)
+                cpd = ev.covparms(cp)
+                ev.loglik_grad_info(cpd, check=False)
+                times = []
+                for _ in range(max(5, args.steps)):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    ev.loglik_grad_info(cpd, check=False)
+                    e1.record(stream)
+                    e1.synchronize()
+                    times.append(e0.elapsed_time(e1))
+            ev.check_status("sweep")
+            kern = statistics.median(times)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                ev2 = V.Vecchia(base["locs"], NN, base["y"], base["X"], V.FAMILY_ISO, 1.5, 0)
+                out = ev2.loglik_grad_info(ev2.covparms(cp), check=False).cpu()
+            e2e = (time.perf_counter() - t0) * 1e3
+            row = dict(n=n, m=m, kernel_ms=kern, nbhd_per_s=n / (kern * 1e-3), end_to_end_ms=e2e,
+                       end_to_end_nbhd_per_s=n / (e2e * 1e-3), loglik=float(out[0]))
+            rows.append(row)
+            log(f"n={n} m={m}: {kern:.3f} ms ({row['nbhd_per_s']:.3e} nbhd/s), end to end "
+                f"{e2e:.1f} ms")
+    line = {"metric": "neighbourhoods/s (loglik+grad+Fisher) over n and m, 2-D Matern 3/2",
+            "value": None, "unit": "neighbourhoods/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "sweep"}, "roofline": None, "cpu_baseline": None,
+            "detail": {"rows": rows}}
     print(json.dumps(line), flush=True)
 
 

@@ -50,7 +50,12 @@ static const resident_fn kResidentBatch[kNumK][3][2] = {
     VEC_BROW(11, resident_sums), VEC_BROW(21, resident_sums), VEC_BROW(31, resident_sums),
     VEC_BROW(41, resident_sums)};
 
-constexpr int kBlocksPerCU = 8;
+#ifndef VECCHIA_BLOCKS_PER_CU
+#define VECCHIA_BLOCKS_PER_CU 8
+#endif
+// Grid of the single-problem launches: workgroups per CU (twice the resident
+// count at K <= 31, so a second round of workgroups fills in behind the first).
+constexpr int kBlocksPerCU = VECCHIA_BLOCKS_PER_CU;
 constexpr int kMaxP = 3;
 constexpr int kMaxParms = 4;
 

@@ -799,7 +799,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int r = decltype(r_)::value;
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (r > 0 && 16 * s < r) {
+        if constexpr (r > 0 && 16 * s + 15 < r) {
+          // every row of the slot lies below r
+          lv[s] = Lp[grp][r * (r - 1) / 2 + row_of(s, l)];
+        } else if constexpr (r > 0 && 16 * s < r) {
           const int row = row_of(s, l);
           const double v = Lp[grp][r * (r - 1) / 2 + (row < r ? row : r - 1)];
           lv[s] = (row < r) ? v : 0.0;
