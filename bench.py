@@ -116,7 +116,7 @@ def main():
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--workload", default="satellite_spacetime",
                     choices=["satellite_spacetime", "batched_uneven", "surrogate_plane",
-                             "sweep"])
+                             "sweep", "predict"])
     ap.add_argument("--train-neighbourhoods", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=2)
     args = ap.parse_args()
@@ -129,6 +129,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "predict":
+        return bench_predict(args)
 
     import numpy as np
     import torch
@@ -191,6 +193,26 @@ def main():
     achieved = F * n / (kernel_ms * 1e-3) / 1e12
     log(f"fused kernel {kernel_ms:.4f} ms, {F} flop/nbhd -> {achieved:.2f} TFLOP/s")
 
+    # the other passes of the fused kernel on the same workload: the
+    # reverse-mode gradient (adjoint, at the GLS estimate) and the loglik-only
+    # forward that the autograd function pairs it with
+    beta = torch.as_tensor(res["betahat"], dtype=torch.float64, device="cuda")
+    passes = {}
+    for name, fn in (("adjoint", lambda: ev.loglik_adjoint(cp, beta, check=False)),
+                     ("loglik_only", lambda: ev.loglik(cp, check=False))):
+        with torch.cuda.stream(stream):
+            fn()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            for _ in range(args.kernel_reps):
+                fn()
+            a1.record(stream)
+        torch.cuda.synchronize()
+        passes[name] = a0.elapsed_time(a1) / args.kernel_reps
+        log(f"{name} pass {passes[name]:.4f} ms ({n / (passes[name] * 1e-3):.4e} nbhd/s)")
+    ev.check_status("adjoint and loglik-only passes")
+
     if args.calibration:
         calibration_kernel()
 
@@ -226,6 +248,7 @@ def main():
         "cpu_baseline": cpu,
         "detail": {"kernel": "sums_kernel<31,1,2,0,false>", "kernel_ms": kernel_ms,
                    "flop_per_neighbourhood": F, "loglik": res["loglik"],
+                   "adjoint_pass_ms": passes["adjoint"], "loglik_only_pass_ms": passes["loglik_only"],
                    "kernel_source_sha256_16": kernel_source_hash()},
     }
     print(json.dumps(line), flush=True)
@@ -485,6 +508,55 @@ def bench_sweep(args):
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "sweep"}, "roofline": None, "cpu_baseline": None,
             "detail": {"rows": rows}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_predict(args):
+    """Kriging prediction at 262,144 new points of the Matern plane
+    (262,144 observations, m = 30, p = 3) from their 30 nearest observed
+    neighbours: predictions per second (weights pass + mean kernel)."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from paper_2407_02740_amd import synthetic as S
+    from paper_2407_02740_amd import vecchia as V
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    w = S.matern_plane()
+    rng = np.random.default_rng(12)
+    npred = 262_144
+    lp = rng.random((npred, 2))
+    Xp = np.column_stack([np.ones(npred), lp[:, 0], lp[:, 1]])
+    NNp = S.nn_among(w["locs"], lp, 30)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], w["family"], w["nu"], 0)
+        cp = ev.covparms(w["covparms"])
+        beta = ev.loglik(cp)[1:4].clone()
+        pr = V.Predictor(ev, lp, Xp, NNp)
+        pr.predict(cp, beta)
+        times = []
+        for _ in range(max(5, args.steps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mean, var = pr.predict(cp, beta, check=False)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+    ev.check_status("predict")
+    ms = statistics.median(times)
+    log(f"{npred} predictions in {ms:.3f} ms")
+    line = {"metric": "kriging predictions/s (m=30 observed neighbours), Matern plane",
+            "value": npred / (ms * 1e-3), "unit": "predictions/s", "n_gpus": 1,
+            "steps": len(times), "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "predict", "n_obs": w["n"], "n_pred": npred, "m": 30},
+            "roofline": None, "cpu_baseline": None,
+            "detail": {"mean_of_means": float(mean.mean()), "mean_var": float(var.mean())}}
     print(json.dumps(line), flush=True)
 
 

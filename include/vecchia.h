@@ -187,6 +187,24 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
                         int64_t i1, double* weights, double* raw, void* workspace,
                         size_t workspace_bytes, int32_t* status, void* stream);
 
+/* Kriging prediction (the conditional Gaussian of Eq. 3 at new points): the
+ * problem pb describes the observations 0..n_obs-1 followed by n - n_obs
+ * prediction points appended to locs, y and X (y of a prediction point is
+ * ignored; pass 0).  NN_pred holds only the prediction rows: row j (point
+ * n_obs + j) is [n_obs + j, its m nearest observed points (indices <
+ * n_obs)], m + 1 int32 per row.  With betahat the mean parameters (e.g. the
+ * GLS estimate of vec_loglik):
+ *   mean[j] = x_j betahat + c' Sigma_s^-1 (y_s - X_s betahat),
+ *   var[j]  = Sigma_jj - c' Sigma_s^-1 c   (the observation process, nugget
+ *             included; subtract sigma2 * tau2 for the latent field),
+ * from the weights mode of the fused kernel.  Requires n_obs >= m.
+ * workspace: vec_kriging_predict_workspace_bytes(pb, n_obs) bytes. */
+size_t vec_kriging_predict_workspace_bytes(const vec_problem* pb, int64_t n_obs);
+int vec_kriging_predict(const vec_problem* pb, const double* locs, const int32_t* NN_pred,
+                        const double* y, const double* X, const double* covparms,
+                        const double* betahat, int64_t n_obs, double* mean, double* var,
+                        void* workspace, size_t workspace_bytes, int32_t* status, void* stream);
+
 /* The combine step of vec_loglik on sums assembled by the caller:
  * raw_sum = raw_a + raw_b (raw_b may be NULL; 2 + p*p + p doubles each,
  * e.g. the parts of the observations evaluated by two different paths),

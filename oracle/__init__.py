@@ -15,6 +15,9 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
   at_beta       pinned: central finite differences in theta at a fixed beta
                 away from beta_hat, the dense reverse-mode expression of the
                 gradient, and agreement with combine at beta_hat.
+  kriging_predict pinned: with every observation as a neighbour it equals the
+                dense Gaussian-process conditional; at an observed location
+                without nugget it interpolates (mean = y, variance = 0).
   kriging_weights pinned: the loglik sums rebuilt from its weights and
                 variances equal raw_sums' (a different code path, C, Neumaier
                 sums); b = 0 and v = 1 + tau2 when the neighbours are far.
@@ -32,6 +35,7 @@ from .oracle import (  # noqa: F401
     cov_matrix,
     fisher_step,
     fit,
+    kriging_predict,
     kriging_weights,
     loglik_grad_info,
     nparms,

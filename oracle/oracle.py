@@ -12,6 +12,8 @@ written from the paper's statement of the method:
                     (generalised least squares, Section 2.1 / Section 3).
 * ``at_beta``    -- the same log-likelihood and theta-gradient at a given
                     (not profiled) mean vector beta.
+* ``kriging_predict`` -- conditional mean and variance at new points given
+                    their observed neighbours.
 * ``kriging_weights`` -- per observation the weights and log conditional
                     variance of its conditional density (Eq. 3), solved
                     densely from the definition.
@@ -245,6 +247,34 @@ def kriging_weights(locs, NN, covparms, family=FAMILY_ISO, nu=0.5, nspace=0, i0=
         out[i - i0, :q] = b
         out[i - i0, m1 - 1] = math.log(v / sigma2)
     return out
+
+
+def kriging_predict(locs, y, X, locs_pred, X_pred, NN_pred, covparms, beta,
+                    family=FAMILY_ISO, nu=0.5, nspace=0):
+    """Conditional mean and variance of the observation process at each
+    prediction point given its listed observed neighbours (the conditional
+    Gaussian of Eq. 3 with the point in the self position):
+      mean = x_p beta + c^T Sigma_s^-1 (y_s - X_s beta),
+      var  = Sigma_pp - c^T Sigma_s^-1 c   (nugget included).
+    NN_pred[j] lists observed indices (entries < 0 ignored)."""
+    locs = np.asarray(locs, dtype=np.float64)
+    locs_pred = np.asarray(locs_pred, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
+    X_pred = np.asarray(X_pred, dtype=np.float64).reshape(len(locs_pred), -1)
+    beta = np.asarray(beta, dtype=np.float64)
+    r = np.asarray(y, dtype=np.float64) - X @ beta
+    mean = np.zeros(len(locs_pred))
+    var = np.zeros(len(locs_pred))
+    for j in range(len(locs_pred)):
+        s = [int(k) for k in NN_pred[j] if k >= 0]
+        pts = np.vstack([locs[s], locs_pred[j][None, :]]) if s else locs_pred[j][None, :]
+        S, _ = cov_matrix(pts, covparms, family, nu, nspace)
+        q = len(s)
+        c = S[:q, q]
+        b = np.linalg.solve(S[:q, :q], c) if q else np.zeros(0)
+        mean[j] = X_pred[j] @ beta + (b @ r[s] if q else 0.0)
+        var[j] = S[q, q] - c @ b
+    return mean, var
 
 
 def loglik_grad_info(locs, NN, y, X, covparms, family=FAMILY_ISO, nu=0.5, nspace=0,

@@ -132,6 +132,34 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
   if (threadIdx.x == 0) raw[e] = red[0];
 }
 
+// Kriging prediction from the weights of the prediction rows: for row j
+// (observation n_obs + j of the augmented problem) with weights b over its
+// neighbours s and w[m] = log(v / sigma2),
+//   mean_j = x_j beta + sum_l b_l (y_s_l - x_s_l beta),  var_j = sigma2 e^w[m].
+__global__ void predict_kernel(int64_t n_obs, int64_t n_pred, int m, int p,
+                               const int32_t* __restrict__ NN, const double* __restrict__ y,
+                               const double* __restrict__ X, const double* __restrict__ beta,
+                               const double* __restrict__ covparms,
+                               const double* __restrict__ w, double* __restrict__ mean,
+                               double* __restrict__ var) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n_pred) return;
+  const int64_t i = n_obs + j;
+  const int32_t* row = NN + j * (int64_t)(m + 1);
+  const double* wj = w + j * (int64_t)(m + 1);
+  double mu = 0.0;
+  for (int t = 0; t < p; ++t) mu += X[i * p + t] * beta[t];
+  for (int l = 0; l < m; ++l) {
+    const int64_t s = row[1 + l];
+    if (s < 0 || s >= n_obs) continue;  // malformed row: flagged by the weights pass
+    double r = y[s];
+    for (int t = 0; t < p; ++t) r -= X[s * p + t] * beta[t];
+    mu += wj[l] * r;
+  }
+  mean[j] = mu;
+  var[j] = covparms[0] * exp(wj[m]);
+}
+
 // sum[e] = a[e] + b[e] (b may be null)
 __global__ void add_raw_kernel(const double* __restrict__ a, const double* __restrict__ b, int count,
                                double* __restrict__ sum) {
@@ -335,7 +363,7 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
                               const double* covparms, const double* beta, int64_t i0, int64_t i1,
                               double* partials, size_t partials_bytes, int* grid_out,
                               int32_t* status, hipStream_t st, double* rows_out = nullptr,
-                              const int32_t* index = nullptr) {
+                              const int32_t* index = nullptr, int64_t nn_row0 = 0) {
   const int grid = grid_for(i1 - i0);
   *grid_out = grid;
   if (grid == 0) return VEC_OK;
@@ -360,6 +388,7 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
   args.rows_out = rows_out;
   args.index = index;
   args.n = pb->n;
+  args.nn_row0 = nn_row0;
   return hip_code(kLaunch[dm.kidx][pc][ng][mode](grid, st, args));
 }
 
@@ -369,7 +398,8 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
                         const double* covparms, const double* beta, int64_t i0, int64_t i1,
                         double* raw, void* workspace, size_t workspace_bytes, int32_t* status,
                         hipStream_t st, double* rows_out = nullptr,
-                        const int32_t* index = nullptr) {
+                        const int32_t* index = nullptr,
+                        int64_t nn_row0 = 0) {
   const int64_t total = i1 - i0;
   const int nraw = nraw_for(dm, mode);
   if (total == 0) {
@@ -379,7 +409,7 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
   double* partials = static_cast<double*>(workspace);
   int grid = 0;
   int rc = enqueue_block_sums(pb, dm, mode, locs, NN, y, X, covparms, beta, i0, i1, partials,
-                              workspace_bytes, &grid, status, st, rows_out, index);
+                              workspace_bytes, &grid, status, st, rows_out, index, nn_row0);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(reduce_kernel, dim3(nraw), dim3(256), 0, st, partials, grid, nraw, raw);
   return hip_code(hipGetLastError());
@@ -618,6 +648,39 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
   return enqueue_sums(pb, dm, kModeWeights, locs, NNarray, y, X, covparms, nullptr, i0, i1, raw,
                       workspace, workspace_bytes, status, static_cast<hipStream_t>(stream),
                       weights);
+}
+
+size_t vec_kriging_predict_workspace_bytes(const vec_problem* pb, int64_t n_obs) {
+  Dims dm;
+  if (!dims_of(pb, &dm) || n_obs < pb->m || n_obs >= pb->n) return 0;
+  const int64_t n_pred = pb->n - n_obs;
+  return align256(vec_workspace_bytes(pb, n_obs, pb->n)) +
+         align256((size_t)n_pred * (pb->m + 1) * sizeof(double)) +
+         align256((size_t)nraw_of(dm.p, 0) * sizeof(double));
+}
+
+int vec_kriging_predict(const vec_problem* pb, const double* locs, const int32_t* NN_pred,
+                        const double* y, const double* X, const double* covparms,
+                        const double* betahat, int64_t n_obs, double* mean, double* var,
+                        void* workspace, size_t workspace_bytes, int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm) || n_obs < pb->m || n_obs >= pb->n) return VEC_EINVAL;
+  if (!locs || !NN_pred || !y || !X || !covparms || !betahat || !mean || !var || !status)
+    return VEC_EINVAL;
+  const size_t need = vec_kriging_predict_workspace_bytes(pb, n_obs);
+  if (!workspace || workspace_bytes < need) return VEC_EWORKSPACE;
+  const int64_t n_pred = pb->n - n_obs;
+  char* w = static_cast<char*>(workspace);
+  const size_t part = align256(vec_workspace_bytes(pb, n_obs, pb->n));
+  double* rows = reinterpret_cast<double*>(w + part);
+  double* raw = reinterpret_cast<double*>(w + part + align256((size_t)n_pred * (pb->m + 1) * 8));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = enqueue_sums(pb, dm, kModeWeights, locs, NN_pred, y, X, covparms, nullptr, n_obs, pb->n,
+                        raw, workspace, part, status, st, rows, nullptr, n_obs);
+  if (rc != VEC_OK) return rc;
+  hipLaunchKernelGGL(predict_kernel, dim3((unsigned)((n_pred + 255) / 256)), dim3(256), 0, st, n_obs,
+                     n_pred, pb->m, dm.p, NN_pred, y, X, betahat, covparms, rows, mean, var);
+  return hip_code(hipGetLastError());
 }
 
 int vec_combine_loglik(const vec_problem* pb, const double* raw_a, const double* raw_b,

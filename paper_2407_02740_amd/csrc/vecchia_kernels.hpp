@@ -194,36 +194,6 @@ __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOM
 
 __device__ __forceinline__ int row_of(int s, int l) { return 16 * s + ((s & 1) ? 15 - l : l); }
 
-// e^-h for h >= 0 (very large h gives 0).  Cody-Waite reduction
-// -h = n ln2 + r, |r| <= ln2/2, with ln2 split into a 32-significant-bit
-// head (n * head is exact for |n| < 2^20) and the remaining tail; e^r by
-// its Taylor series to degree 13 (truncation below 5e-18 relative); 2^n by
-// ldexp.  Arguments below -800 are clamped: 2^-1154 underflows to 0.
-__host__ __device__ __forceinline__ double exp_neg(double h) {
-  constexpr double kLog2e = 1.4426950408889634;
-  constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
-  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
-  const double x = fmax(-h, -800.0);
-  const double n = rint(x * kLog2e);
-  double r = __builtin_fma(-n, kLn2Hi, x);
-  r = __builtin_fma(-n, kLn2Lo, r);
-  double p = 1.0 / 6227020800.0;                  // 1/13!
-  p = __builtin_fma(p, r, 1.0 / 479001600.0);     // 1/12!
-  p = __builtin_fma(p, r, 1.0 / 39916800.0);      // 1/11!
-  p = __builtin_fma(p, r, 1.0 / 3628800.0);       // 1/10!
-  p = __builtin_fma(p, r, 1.0 / 362880.0);        // 1/9!
-  p = __builtin_fma(p, r, 1.0 / 40320.0);         // 1/8!
-  p = __builtin_fma(p, r, 1.0 / 5040.0);          // 1/7!
-  p = __builtin_fma(p, r, 1.0 / 720.0);           // 1/6!
-  p = __builtin_fma(p, r, 1.0 / 120.0);           // 1/5!
-  p = __builtin_fma(p, r, 1.0 / 24.0);            // 1/4!
-  p = __builtin_fma(p, r, 1.0 / 6.0);             // 1/3!
-  p = __builtin_fma(p, r, 0.5);                   // 1/2!
-  p = __builtin_fma(p, r, 1.0);
-  p = __builtin_fma(p, r, 1.0);
-  return ldexp(p, (int)n);
-}
-
 // h = sqrt(h2) and 1/h.  1e-300 is added to h2 so that coincident
 // locations give h ~ 1e-150 and a finite 1/h (every use multiplies 1/h by a
 // squared coordinate difference that is then 0); for any h2 above 1e-284 the
@@ -276,6 +246,7 @@ struct SumsArgs {
   double* rows_out;        // weights mode: [i1 - i0][m + 1]
   const int32_t* index;    // optional: observations at positions [i0, i1) of this list
   int64_t n;               // observations of the problem (bounds of index entries)
+  int64_t nn_row0;         // observation whose NNarray row is NN[0] (0: the whole array)
   BatchClass batch;
 };
 
@@ -377,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // 1..q of the NNarray row are read (column 0 otherwise).
   auto fetch_ids = [&](int64_t ii, int lan, int64_t(&id)[NS], bool& bad) {
     const int qq = (int)(ii < (int64_t)m ? ii : (int64_t)m);
-    const int32_t* row = NN + ii * (int64_t)(m + 1);
+    const int32_t* row = NN + (ii - a.nn_row0) * (int64_t)(m + 1);
     bad = (row[0] != (int32_t)ii);
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;

@@ -356,3 +356,18 @@ def surrogate_plane(seed: int = 5, n: int = 4_194_304, m: int = 30, n_features: 
     y = 0.3 + math.sqrt(covparms[0]) * f + math.sqrt(covparms[0] * covparms[2]) * \
         rng.standard_normal(n)
     return _pack("surrogate_plane", locs, NN, y, np.ones((n, 1)), covparms, FAMILY_ISO, nu, 0, m)
+
+
+def nn_among(locs_obs: np.ndarray, locs_pred: np.ndarray, m: int) -> np.ndarray:
+    """Prediction rows of an NNarray: for prediction point j (appended after
+    the n_obs observations), [n_obs + j, its m nearest observed points by
+    increasing distance] (int32 [n_pred][m + 1])."""
+    from scipy.spatial import cKDTree
+
+    n_obs = len(locs_obs)
+    _, idx = cKDTree(locs_obs).query(locs_pred, k=m, workers=-1)
+    idx = np.asarray(idx).reshape(len(locs_pred), m)
+    out = np.empty((len(locs_pred), m + 1), dtype=np.int32)
+    out[:, 0] = n_obs + np.arange(len(locs_pred))
+    out[:, 1:] = idx
+    return out

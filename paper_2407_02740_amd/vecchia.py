@@ -78,6 +78,11 @@ def lib():
         L.vec_kriging_weights.restype = ctypes.c_int
         L.vec_kriging_weights.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64,
                                           ctypes.c_int64, _VP, _VP, _VP, ctypes.c_size_t, _VP, _VP]
+        L.vec_kriging_predict_workspace_bytes.restype = ctypes.c_size_t
+        L.vec_kriging_predict_workspace_bytes.argtypes = [pp, ctypes.c_int64]
+        L.vec_kriging_predict.restype = ctypes.c_int
+        L.vec_kriging_predict.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP,
+                                          _VP, _VP, ctypes.c_size_t, _VP, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
         L.vec_fisher_fit.restype = ctypes.c_int
@@ -312,6 +317,48 @@ class Vecchia:
         if check:
             self.check_status("vec_fisher_fit")
         return covparms
+
+
+class Predictor:
+    """Kriging prediction at new points from their m nearest observed
+    neighbours (vec_kriging_predict): the prediction points are appended to
+    a copy of the observation arrays on the device."""
+
+    def __init__(self, ev: Vecchia, locs_pred, X_pred, NN_pred):
+        dev = ev.device
+        lp = torch.as_tensor(locs_pred, dtype=torch.float64).reshape(-1, ev.locs.shape[1]).to(dev)
+        xp = torch.as_tensor(X_pred, dtype=torch.float64).reshape(-1, ev.p).to(dev)
+        self.n_obs, self.n_pred = ev.n, lp.shape[0]
+        self.locs = torch.cat([ev.locs, lp]).contiguous()
+        self.y = torch.cat([ev.y, torch.zeros(self.n_pred, dtype=torch.float64, device=dev)])
+        self.X = torch.cat([ev.X, xp]).contiguous()
+        self.NN = torch.as_tensor(NN_pred, dtype=torch.int32).to(dev).contiguous()
+        if self.NN.shape != (self.n_pred, ev.pb.m + 1):
+            raise ValueError("NN_pred must be [n_pred][m + 1]")
+        self.pb = Problem(n=self.n_obs + self.n_pred, m=ev.pb.m, d=ev.pb.d, p=ev.p,
+                          family=ev.pb.family, smoothness=ev.pb.smoothness,
+                          nspace=ev.pb.nspace, reserved=0)
+        self.ev = ev
+        nb = lib().vec_kriging_predict_workspace_bytes(ctypes.byref(self.pb), self.n_obs)
+        if nb == 0:
+            raise VecchiaError(VEC_EINVAL, "vec_kriging_predict_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def predict(self, covparms, betahat, check: bool = True):
+        ev = self.ev
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            ev.covparms(covparms)
+        beta = torch.as_tensor(betahat, dtype=torch.float64).to(ev.device).contiguous()
+        mean = torch.empty(self.n_pred, dtype=torch.float64, device=ev.device)
+        var = torch.empty_like(mean)
+        _check(lib().vec_kriging_predict(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), beta.data_ptr(), self.n_obs,
+            mean.data_ptr(), var.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+            ev.status.data_ptr(), _stream()), "vec_kriging_predict")
+        if check:
+            ev.check_status("vec_kriging_predict")
+        return mean, var
 
 
 class VecchiaLoglik(torch.autograd.Function):

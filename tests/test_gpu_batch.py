@@ -169,3 +169,23 @@ def test_full_size_batched_uneven():
         ev = V.Vecchia(d["locs"], d["NN"], d["y"], d["X"], d["family"], d["nu"], d["nspace"])
         single = V.unpack_out(ev.loglik_grad_info(d["covparms"]), 1, ev.P)
         check_outputs(V.unpack_out(out[b], 1, vb.P), single, f"single {b}")
+
+
+def test_autotuner_picks_a_measured_schedule_and_stays_exact():
+    """The tuner times each size class under every candidate, keeps the
+    fastest, and the batch evaluated under the chosen plan still matches the
+    oracle dataset by dataset."""
+    import paper_2407_02740_amd.autotune as AT
+
+    w = _small_batch(nsets=12, seed=45, n_min=2000, n_max=5000)
+    vb = _vb(w)
+    sched, table = AT.tune_batch(vb, w["covparms"], tiles=(8, 64), blocks=(0,), reps=2, log=_say)
+    present = {min(c for c, K in enumerate(V.CLASS_K) if m + 1 <= K) for m in w["m"]}
+    assert set(table) == present
+    for c, rows in table.items():
+        assert len(rows) == 2 and all(ms > 0 for _, _, ms in rows)
+        best = min(rows, key=lambda r: r[2])
+        assert sched.tile[c] == best[0] and vb.plan.sched.tile[c] == best[0]
+    out = vb.loglik_grad_info(w["covparms"]).cpu().numpy()
+    for b in range(w["nsets"]):
+        check_outputs(V.unpack_out(out[b], 1, vb.P), _oracle_member(w, b), f"tuned {b}")

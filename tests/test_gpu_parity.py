@@ -218,3 +218,21 @@ def test_full_size_satellite_spacetime():
     check_outputs(got, ref, "full")
     th = oracle.fisher_step(w["covparms"], ref["grad"], ref["info"])
     np.testing.assert_allclose(cp.cpu().numpy(), th, rtol=1e-8)
+
+
+@pytest.mark.parametrize("m,nu,p", [(10, 0.5, 1), (30, 1.5, 2), (40, 2.5, 1)])
+def test_kriging_predict_matches_oracle(m, nu, p):
+    w = _random_problem(3000, m, V.FAMILY_ISO, nu, p, seed=70 + m)
+    rng = np.random.default_rng(71)
+    npred = 1234
+    lp = rng.random((npred, 2))
+    Xp = np.column_stack([np.ones(npred)] + [rng.standard_normal(npred) for _ in range(p - 1)])
+    NNp = S.nn_among(w["locs"], lp, m)
+    ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], w["family"], w["nu"], 0)
+    beta = ev.loglik(w["covparms"]).cpu().numpy()[1:1 + p]
+    mean, var = V.Predictor(ev, lp, Xp, NNp).predict(w["covparms"], beta)
+    ref_m, ref_v = oracle.kriging_predict(w["locs"], w["y"], w["X"], lp, Xp, NNp[:, 1:],
+                                          w["covparms"], beta, w["family"], w["nu"])
+    np.testing.assert_allclose(mean.cpu().numpy(), ref_m, rtol=1e-10,
+                               atol=1e-10 * np.abs(ref_m).max())
+    np.testing.assert_allclose(var.cpu().numpy(), ref_v, rtol=1e-10)

@@ -409,6 +409,39 @@ def test_kriging_weights_of_far_neighbours_vanish():
     np.testing.assert_allclose(W[:, 2], math.log(1.3), rtol=1e-15)
 
 
+@pytest.mark.parametrize("nu", [0.5, 2.5])
+def test_kriging_predict_full_conditioning_is_the_dense_conditional(nu):
+    rng = np.random.default_rng(41)
+    n, npred = 60, 7
+    locs = rng.random((n, 2))
+    X = np.column_stack([np.ones(n), rng.standard_normal(n)])
+    y = rng.standard_normal(n)
+    lp = rng.random((npred, 2))
+    Xp = np.column_stack([np.ones(npred), rng.standard_normal(npred)])
+    cp = np.array((1.4, 0.2, 0.07))
+    beta = np.array([0.3, -0.2])
+    NNp = np.tile(np.arange(n)[::-1], (npred, 1))   # every observation, any order
+    mean, var = oracle.kriging_predict(locs, y, X, lp, Xp, NNp, cp, beta, ISO, nu)
+    S, _ = oracle.cov_matrix(np.vstack([locs, lp]), cp, ISO, nu)
+    Soo, Spo = S[:n, :n], S[n:, :n]
+    m_ref = Xp @ beta + Spo @ np.linalg.solve(Soo, y - X @ beta)
+    v_ref = np.diag(S[n:, n:]) - np.einsum("ij,ji->i", Spo, np.linalg.solve(Soo, Spo.T))
+    np.testing.assert_allclose(mean, m_ref, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(var, v_ref, rtol=1e-9, atol=1e-12)
+
+
+def test_kriging_predict_interpolates_without_nugget():
+    rng = np.random.default_rng(42)
+    locs = rng.random((30, 2))
+    y = rng.standard_normal(30)
+    X = np.ones((30, 1))
+    NNp = np.array([[3, 7, 11, 0], [8, 2, 5, 9]])
+    mean, var = oracle.kriging_predict(locs, y, X, locs[[7, 5]], np.ones((2, 1)), NNp,
+                                       (1.0, 0.3, 0.0), [0.1], ISO, 1.5)
+    np.testing.assert_allclose(mean, y[[7, 5]], rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(var, 0.0, atol=1e-8)
+
+
 def test_fisher_symmetric_positive_semidefinite():
     locs, NN, y, X, cp = _problem(500, 15, d=3, p=2, family=ST, nu=0.5, seed=10)
     info = oracle.loglik_grad_info(locs, NN, y, X, cp, ST, 0.5, nspace=2)["info"]

@@ -61,3 +61,38 @@ def test_workloads_are_seeded_and_shaped():
     np.testing.assert_allclose((xyz ** 2).sum(1), 1.0, rtol=1e-12)
     lat = np.degrees(np.arcsin(xyz[:, 2]))
     assert np.abs(lat).max() <= 60.0 + 1e-9
+
+
+def test_batched_uneven_offsets_and_worker_independence():
+    a = S.batched_uneven(seed=9, nsets=6, n_min=300, n_max=900, workers=1)
+    b = S.batched_uneven(seed=9, nsets=6, n_min=300, n_max=900, workers=3)
+    for k in ("locs", "NN", "y", "n", "m", "covparms", "nu"):
+        np.testing.assert_array_equal(a[k], b[k])
+    n, m = a["n"], a["m"]
+    assert a["locs"].shape == (n.sum(), 2) and a["NN"].size == int((n * (m + 1)).sum())
+    assert np.all(np.isin(m, [10, 20, 30, 40]))
+    for bi in range(6):
+        d = S.batch_member(a, bi)
+        NN = d["NN"]
+        assert NN.shape == (n[bi], m[bi] + 1)
+        assert np.all(NN[:, 0] == np.arange(n[bi]))
+        valid = NN[:, 1:] >= 0
+        assert np.all(NN[:, 1:][valid] < np.arange(n[bi])[:, None].repeat(m[bi], 1)[valid])
+        assert 0.02 <= d["covparms"][1] <= 0.3 and 0.01 <= d["covparms"][2] <= 0.5
+
+
+def test_surrogate_plane_shape():
+    w = S.surrogate_plane(n=2000)
+    assert w["NN"].shape == (2000, 31) and w["locs"].shape == (2000, 2)
+    assert tuple(w["covparms"]) == (1.0, 0.05, 0.05) and w["nu"] == 1.5
+
+
+def test_nn_among_lists_the_nearest_observed_points():
+    rng = np.random.default_rng(3)
+    obs = rng.random((500, 2))
+    pred = rng.random((20, 2))
+    NN = S.nn_among(obs, pred, 7)
+    assert NN.shape == (20, 8) and np.all(NN[:, 0] == 500 + np.arange(20))
+    for j in range(20):
+        d = ((obs - pred[j]) ** 2).sum(1)
+        np.testing.assert_array_equal(NN[j, 1:], np.argsort(d, kind="stable")[:7])
