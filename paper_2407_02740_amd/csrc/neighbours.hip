@@ -1,0 +1,378 @@
+// Nearest previously ordered neighbours on the device: for every
+// observation i of an ordered point set, the min(i, m) observations j < i
+// closest to it (Section 2.1: the conditioning sets of the Vecchia
+// factorisation), written as NNarray rows [i, nearest, ..., -1 padding].
+//
+// Observations are taken in doubling blocks [b0, b1) (the first block is
+// [0, head)).  For a block, a uniform grid with about kPerCell points per
+// cell is built over observations [0, b1) (cell ids, counting sort by cell
+// with coordinates copied into cell order), and each observation i of the
+// block searches the grid in shells of growing Chebyshev radius around its
+// own cell, keeping the m best candidates j < i sorted by (distance, index)
+// in LDS.  After shell r every point still unvisited lies farther than r
+// cell sides, so the search stops once the m-th best distance is below that.
+// Candidates within a cell may be visited in any order; the (distance,
+// index) order makes the result unique.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "vecchia.h"
+
+namespace vecchia_nn {
+
+constexpr int kMaxD = 3;
+constexpr int kQueryThreads = 64;
+constexpr int kPerCell = 3;
+constexpr int kMaxM = 64;
+
+struct Grid {
+  double lo[kMaxD];
+  double side;
+  int g[kMaxD];       // cells per dimension
+  int64_t stride[kMaxD];
+  int64_t ncells;
+};
+
+__device__ __forceinline__ int cell_coord(double x, double lo, double side, int g) {
+  int c = (int)floor((x - lo) / side);
+  return c < 0 ? 0 : (c >= g ? g - 1 : c);
+}
+
+template <int D>
+__global__ void bbox_kernel(int64_t n, const double* __restrict__ locs, double* __restrict__ box) {
+  __shared__ double lo[256][D], hi[256][D];
+  double l[D], h[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    l[k] = INFINITY;
+    h[k] = -INFINITY;
+  }
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double x = locs[i * D + k];
+      l[k] = fmin(l[k], x);
+      h[k] = fmax(h[k], x);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    lo[threadIdx.x][k] = l[k];
+    hi[threadIdx.x][k] = h[k];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        lo[threadIdx.x][k] = fmin(lo[threadIdx.x][k], lo[threadIdx.x + w][k]);
+        hi[threadIdx.x][k] = fmax(hi[threadIdx.x][k], hi[threadIdx.x + w][k]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < D) {
+    box[threadIdx.x] = lo[0][threadIdx.x];
+    box[D + threadIdx.x] = hi[0][threadIdx.x];
+  }
+}
+
+__global__ void zero_i32_kernel(int32_t* __restrict__ x, int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 0;
+}
+
+template <int D>
+__global__ void cell_kernel(int64_t b1, const double* __restrict__ locs, const Grid g,
+                            int32_t* __restrict__ cell, int32_t* __restrict__ count) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= b1) return;
+  int64_t c = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) c += (int64_t)cell_coord(locs[j * D + k], g.lo[k], g.side, g.g[k]) * g.stride[k];
+  cell[j] = (int32_t)c;
+  atomicAdd(&count[c], 1);
+}
+
+// start[c] = sum of count[0..c) (one workgroup, fixed order); start[ncells]
+// = total; cursor[c] = start[c]
+__global__ __launch_bounds__(1024) void scan_kernel(int64_t ncells, const int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ cursor) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (ncells + 1023) / 1024;
+  const int64_t a = t * per, b = (a + per < ncells) ? a + per : ncells;
+  int32_t s = 0;
+  for (int64_t c = a; c < b; ++c) s += count[c];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int32_t v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = (t > 0) ? part[t - 1] : 0;
+  for (int64_t c = a; c < b; ++c) {
+    start[c] = run;
+    cursor[c] = run;
+    run += count[c];
+  }
+  if (t == 1023) start[ncells] = part[1023];
+}
+
+template <int D>
+__global__ void scatter_kernel(int64_t b1, const double* __restrict__ locs,
+                               const int32_t* __restrict__ cell, int32_t* __restrict__ cursor,
+                               int32_t* __restrict__ sidx, double* __restrict__ sxyz) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= b1) return;
+  const int32_t pos = atomicAdd(&cursor[cell[j]], 1);
+  sidx[pos] = (int32_t)j;
+#pragma unroll
+  for (int k = 0; k < D; ++k) sxyz[(int64_t)pos * D + k] = locs[j * D + k];
+}
+
+// (d, j) < (e, k) in the order of the result
+__device__ __forceinline__ bool before(double d, int32_t j, double e, int32_t k) {
+  return d < e || (d == e && j < k);
+}
+
+template <int D>
+__global__ __launch_bounds__(kQueryThreads) void query_kernel(
+    int64_t b0, int64_t b1, int m, const double* __restrict__ locs, const Grid g,
+    const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
+    const double* __restrict__ sxyz, int32_t* __restrict__ NN) {
+  // per thread: the m best distances and indices (dynamic LDS, m columns of
+  // kQueryThreads entries each)
+  extern __shared__ double dyn[];
+  double* __restrict__ bdv = dyn;
+  int32_t* __restrict__ bjv = reinterpret_cast<int32_t*>(dyn + (size_t)m * kQueryThreads);
+  const int t = threadIdx.x;
+#define bd(q) bdv[(q) * kQueryThreads + t]
+#define bj(q) bjv[(q) * kQueryThreads + t]
+  const int64_t i = b0 + blockIdx.x * (int64_t)kQueryThreads + t;
+  if (i >= b1) return;
+  const int me = (int)(i < m ? i : m);
+  double xq[D];
+  int h[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    xq[k] = locs[i * D + k];
+    h[k] = cell_coord(xq[k], g.lo[k], g.side, g.g[k]);
+  }
+  int cnt = 0;
+  int gmax = 1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) gmax = g.g[k] > gmax ? g.g[k] : gmax;
+  for (int r = 0; me > 0 && r <= gmax; ++r) {
+    // cells at Chebyshev distance exactly r from the home cell
+    int o[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) o[k] = -r;
+    for (;;) {
+      bool on_shell = false, inside = true;
+      int64_t c = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        on_shell = on_shell || o[k] == -r || o[k] == r;
+        const int ck = h[k] + o[k];
+        inside = inside && ck >= 0 && ck < g.g[k];
+        c += (int64_t)ck * g.stride[k];
+      }
+      if (on_shell && inside) {
+        const int32_t pa = start[c], pb = start[c + 1];
+        for (int32_t p = pa; p < pb; ++p) {
+          const int32_t j = sidx[p];
+          if (j >= i) continue;
+          double d2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const double dz = sxyz[(int64_t)p * D + k] - xq[k];
+            d2 = fma(dz, dz, d2);
+          }
+          if (cnt == me && !before(d2, j, bd(me - 1), bj(me - 1))) continue;
+          // insert, keeping the list sorted
+          int q = (cnt < me) ? cnt : me - 1;
+          while (q > 0 && before(d2, j, bd(q - 1), bj(q - 1))) {
+            bd(q) = bd(q - 1);
+            bj(q) = bj(q - 1);
+            --q;
+          }
+          bd(q) = d2;
+          bj(q) = j;
+          if (cnt < me) ++cnt;
+        }
+      }
+      // next offset of the cube [-r, r]^D
+      int k = 0;
+      while (k < D) {
+        if (o[k] < r) {
+          ++o[k];
+          break;
+        }
+        o[k] = -r;
+        ++k;
+      }
+      if (k == D) break;
+    }
+    const double reach = r * g.side;
+    if (cnt == me && bd(me - 1) < reach * reach) break;
+  }
+  int32_t* row = NN + i * (int64_t)(m + 1);
+  row[0] = (int32_t)i;
+  for (int q = 0; q < m; ++q) row[1 + q] = (q < cnt) ? bj(q) : -1;
+#undef bd
+#undef bj
+}
+
+}  // namespace vecchia_nn
+
+using namespace vecchia_nn;
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t head_of(int64_t n, int m) {
+  const int64_t h = 4 * (int64_t)(m + 1) > 64 ? 4 * (int64_t)(m + 1) : 64;
+  return h < n ? h : n;
+}
+
+// the largest cell count any block's grid can have
+int64_t max_cells(int64_t n) { return n / kPerCell + 8 * 8 * 8 + 1; }
+
+struct Work {
+  double* box;
+  int32_t *cell, *count, *start, *cursor, *sidx;
+  double* sxyz;
+  size_t bytes;
+};
+
+Work carve(void* ws, int64_t n, int d) {
+  Work w = {};
+  char* p = static_cast<char*>(ws);
+  size_t o = 0;
+  auto take = [&](size_t b) -> char* {
+    char* q = p ? p + o : nullptr;
+    o += al256(b);
+    return q;
+  };
+  const int64_t nc = max_cells(n);
+  w.box = reinterpret_cast<double*>(take(2 * kMaxD * sizeof(double)));
+  w.cell = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+  w.count = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
+  w.start = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
+  w.cursor = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
+  w.sidx = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+  w.sxyz = reinterpret_cast<double*>(take((size_t)n * d * sizeof(double)));
+  w.bytes = o;
+  return w;
+}
+
+// grid over points [0, b1) inside the box: equal cell sides, about kPerCell
+// points per cell (dimensions of negligible extent get one cell)
+Grid make_grid(const double* lo, const double* hi, int d, int64_t b1) {
+  Grid g = {};
+  double ext[kMaxD], emax = 0.0;
+  for (int k = 0; k < d; ++k) {
+    ext[k] = hi[k] - lo[k];
+    emax = ext[k] > emax ? ext[k] : emax;
+  }
+  double vol = 1.0;
+  int dd = 0;
+  for (int k = 0; k < d; ++k) {
+    if (ext[k] > 1e-12 * emax) {
+      vol *= ext[k];
+      ++dd;
+    }
+  }
+  const double target = (double)(b1 / kPerCell > 1 ? b1 / kPerCell : 1);
+  double side = (dd > 0 && vol > 0.0) ? pow(vol / target, 1.0 / dd) : 1.0;
+  if (!(side > 0.0)) side = 1.0;
+  int64_t nc = 1;
+  for (int k = 0; k < d; ++k) {
+    int gk = (ext[k] > 1e-12 * emax) ? (int)ceil(ext[k] / side) : 1;
+    gk = gk < 1 ? 1 : gk;
+    g.g[k] = gk;
+    g.lo[k] = lo[k];
+    nc *= gk;
+  }
+  // the rounding up can overshoot the target; widen until within bounds
+  while (nc > max_cells(b1) - 1) {
+    side *= 1.1;
+    nc = 1;
+    for (int k = 0; k < d; ++k) {
+      int gk = (ext[k] > 1e-12 * emax) ? (int)ceil(ext[k] / side) : 1;
+      g.g[k] = gk < 1 ? 1 : gk;
+      nc *= g.g[k];
+    }
+  }
+  g.side = side;
+  int64_t st = 1;
+  for (int k = 0; k < d; ++k) {
+    g.stride[k] = st;
+    st *= g.g[k];
+  }
+  g.ncells = st;
+  return g;
+}
+
+template <int D>
+int run(int64_t n, int m, const double* locs, int32_t* NN, const Work& w, hipStream_t st) {
+  hipLaunchKernelGGL(bbox_kernel<D>, dim3(1), dim3(256), 0, st, n, locs, w.box);
+  double box[2 * kMaxD];
+  if (hipMemcpyAsync(box, w.box, 2 * D * sizeof(double), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return VEC_EHIP;
+  for (int k = 0; k < D; ++k)
+    if (!isfinite(box[k]) || !isfinite(box[D + k])) return VEC_EINVAL;
+  int64_t b0 = 0, b1 = head_of(n, m);
+  while (b0 < n) {
+    const Grid g = make_grid(box, box + D, D, b1);
+    const unsigned nb = (unsigned)((b1 + 255) / 256);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(256), dim3(256), 0, st, w.count, g.ncells + 1);
+    hipLaunchKernelGGL(cell_kernel<D>, dim3(nb), dim3(256), 0, st, b1, locs, g, w.cell, w.count);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, g.ncells, w.count, w.start,
+                       w.cursor);
+    hipLaunchKernelGGL(scatter_kernel<D>, dim3(nb), dim3(256), 0, st, b1, locs, w.cell, w.cursor,
+                       w.sidx, w.sxyz);
+    const unsigned nq = (unsigned)((b1 - b0 + kQueryThreads - 1) / kQueryThreads);
+    const size_t lds = (size_t)(m > 0 ? m : 1) * kQueryThreads * (sizeof(double) + sizeof(int32_t));
+    hipLaunchKernelGGL(query_kernel<D>, dim3(nq), dim3(kQueryThreads), lds, st, b0, b1, m, locs, g,
+                       w.start, w.sidx, w.sxyz, NN);
+    if (hipGetLastError() != hipSuccess) return VEC_EHIP;
+    b0 = b1;
+    b1 = 2 * b1 < n ? 2 * b1 : n;
+  }
+  return VEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vec_ordered_nn_workspace_bytes(int64_t n, int32_t d, int32_t m) {
+  if (n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxD || m < 0 || m > kMaxM) return 0;
+  return carve(nullptr, n, d).bytes;
+}
+
+int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t* NNarray,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxD || m < 0 || m > kMaxM || !locs ||
+      !NNarray)
+    return VEC_EINVAL;
+  const size_t need = vec_ordered_nn_workspace_bytes(n, d, m);
+  if (!workspace || workspace_bytes < need) return VEC_EWORKSPACE;
+  const Work w = carve(workspace, n, d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (d == 1) return run<1>(n, m, locs, NNarray, w, st);
+  if (d == 2) return run<2>(n, m, locs, NNarray, w, st);
+  return run<3>(n, m, locs, NNarray, w, st);
+}
+
+}  // extern "C"
