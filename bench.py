@@ -116,7 +116,7 @@ def main():
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--workload", default="satellite_spacetime",
                     choices=["satellite_spacetime", "batched_uneven", "surrogate_plane",
-                             "sweep", "predict"])
+                             "sweep", "predict", "neighbours"])
     ap.add_argument("--train-neighbourhoods", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=2)
     args = ap.parse_args()
@@ -131,6 +131,8 @@ def main():
         return bench_sweep(args)
     if args.workload == "predict":
         return bench_predict(args)
+    if args.workload == "neighbours":
+        return bench_neighbours(args)
 
     import numpy as np
     import torch
@@ -557,6 +559,55 @@ def bench_predict(args):
             "config": {"workload": "predict", "n_obs": w["n"], "n_pred": npred, "m": 30},
             "roofline": None, "cpu_baseline": None,
             "detail": {"mean_of_means": float(mean.mean()), "mean_var": float(var.mean())}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_neighbours(args):
+    """Ordered nearest-neighbour search (the NNarray the hot path consumes)
+    on the device for n = 1,048,576 maxmin-ordered uniform 2-D points, m =
+    30, against the host k-d tree search of the input module."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from paper_2407_02740_amd import synthetic as S
+    from paper_2407_02740_amd import vecchia as V
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    n, m = 1 << 20, 30
+    rng = np.random.default_rng(13)
+    locs = rng.random((n, 2))
+    locs = locs[S.maxmin_approx(locs, 13)]
+    x = torch.as_tensor(locs, device="cuda")
+    V.ordered_nn(x, m)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(3, args.steps)):
+        t0 = time.perf_counter()
+        NN = V.ordered_nn(x, m)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_gpu = statistics.median(times)
+    log(f"device search {t_gpu * 1e3:.1f} ms")
+    cpu = None
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        tc = time.perf_counter()
+        ref = S.find_ordered_nn(locs, m, workers=threads)
+        t_cpu = time.perf_counter() - tc
+        assert np.array_equal(ref, NN.cpu().numpy()), "device and host searches differ"
+        cpu = {"value": n / t_cpu, "unit": "points/s", "cores": threads,
+               "kind": "host k-d tree search (scipy cKDTree over doubling prefixes)",
+               "sample": f"all {n} points, {t_cpu:.2f} s wall"}
+        log(f"host search {t_cpu:.2f} s")
+    line = {"metric": "ordered nearest-neighbour search, points/s (n=1M, m=30, 2-D)",
+            "value": n / t_gpu, "unit": "points/s", "n_gpus": 1, "steps": len(times),
+            "warmup": 1, "ms_per_step": 1e3 * t_gpu, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "neighbours", "n": n, "m": m, "d": 2}, "roofline": None,
+            "cpu_baseline": cpu, "detail": {}}
     print(json.dumps(line), flush=True)
 
 

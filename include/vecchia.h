@@ -205,6 +205,19 @@ int vec_kriging_predict(const vec_problem* pb, const double* locs, const int32_t
                         const double* betahat, int64_t n_obs, double* mean, double* var,
                         void* workspace, size_t workspace_bytes, int32_t* status, void* stream);
 
+/* Nearest previously ordered neighbours on the device (the conditioning
+ * sets of Section 2.1): for every observation i of the ordered points
+ * locs[n][d] (d = 1, 2 or 3), the min(i, m) observations j < i nearest to
+ * it in Euclidean distance, written as NNarray[i] = [i, nearest first, ...,
+ * -1 padding] (n rows of m + 1 int32; ties in distance go to the smaller
+ * index, so the result is unique).  Scale the coordinates beforehand for
+ * anisotropic ranges.  m <= 64.  The call reads the bounding box back to
+ * the host, so it synchronises `stream` once.  workspace:
+ * vec_ordered_nn_workspace_bytes(n, d, m) bytes. */
+size_t vec_ordered_nn_workspace_bytes(int64_t n, int32_t d, int32_t m);
+int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t* NNarray,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
 /* The combine step of vec_loglik on sums assembled by the caller:
  * raw_sum = raw_a + raw_b (raw_b may be NULL; 2 + p*p + p doubles each,
  * e.g. the parts of the observations evaluated by two different paths),

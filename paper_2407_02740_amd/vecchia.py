@@ -83,6 +83,12 @@ def lib():
         L.vec_kriging_predict.restype = ctypes.c_int
         L.vec_kriging_predict.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP,
                                           _VP, _VP, ctypes.c_size_t, _VP, _VP]
+        L.vec_ordered_nn_workspace_bytes.restype = ctypes.c_size_t
+        L.vec_ordered_nn_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32,
+                                                     ctypes.c_int32]
+        L.vec_ordered_nn.restype = ctypes.c_int
+        L.vec_ordered_nn.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
+                                     ctypes.c_size_t, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
         L.vec_fisher_fit.restype = ctypes.c_int
@@ -317,6 +323,23 @@ class Vecchia:
         if check:
             self.check_status("vec_fisher_fit")
         return covparms
+
+
+def ordered_nn(locs, m: int, device: str = "cuda") -> torch.Tensor:
+    """NNarray [n][m + 1] (int32, on the device) of the ordered points locs
+    ([n][d], d <= 3) by the library's neighbour search (vec_ordered_nn)."""
+    x = torch.as_tensor(locs, dtype=torch.float64).to(device).contiguous()
+    if x.dim() == 1:
+        x = x[:, None].contiguous()
+    n, d = x.shape
+    nb = lib().vec_ordered_nn_workspace_bytes(n, d, m)
+    if nb == 0:
+        raise VecchiaError(VEC_EINVAL, "vec_ordered_nn_workspace_bytes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+    NN = torch.empty(n, m + 1, dtype=torch.int32, device=x.device)
+    _check(lib().vec_ordered_nn(n, d, m, x.data_ptr(), NN.data_ptr(), ws.data_ptr(), nb,
+                                _stream()), "vec_ordered_nn")
+    return NN
 
 
 class Predictor:
