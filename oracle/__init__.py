@@ -8,9 +8,14 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
   raw_sums      pinned: dense exact GP at full conditioning (Section 2.1, A5),
                 joint-minus-marginal dense forms at any m, AR(1) closed form
                 for the 1-D exponential, m = 0 closed form, sigma2 identities,
-                finite differences of the log-likelihood.
+                finite differences of the log-likelihood; anisotropic sums
+                collapse to the isotropic ones at equal ranges and transform
+                as they must under coordinate permutation and stretching.
   cov_matrix    pinned: Matern via the Bessel-K definition (scipy), and
-                finite differences for the parameter derivatives.
+                finite differences for the parameter derivatives; the
+                anisotropic family (a range per coordinate) equals the
+                unit-range isotropic one on rescaled coordinates, and the
+                isotropic one when the ranges are equal.
   combine       pinned through the dense exact GP and the AR(1) closed form.
   at_beta       pinned: central finite differences in theta at a fixed beta
                 away from beta_hat, the dense reverse-mode expression of the
@@ -26,6 +31,7 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
 """
 
 from .oracle import (  # noqa: F401
+    FAMILY_ANISO,
     FAMILY_ISO,
     FAMILY_SPACETIME,
     OracleError,

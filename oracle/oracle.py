@@ -40,6 +40,7 @@ import numpy as np
 
 FAMILY_ISO = 0
 FAMILY_SPACETIME = 1
+FAMILY_ANISO = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vecchia_oracle.c")
@@ -87,7 +88,7 @@ def _load():
                 ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp,
                 dp, dp]
             lib.oracle_nparms.restype = ctypes.c_int
-            lib.oracle_nparms.argtypes = [ctypes.c_int]
+            lib.oracle_nparms.argtypes = [ctypes.c_int, ctypes.c_int]
             lib.oracle_nraw.restype = ctypes.c_int
             lib.oracle_nraw.argtypes = [ctypes.c_int, ctypes.c_int]
             _lib = lib
@@ -98,7 +99,13 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def nparms(family: int) -> int:
+def nparms(family: int, d: int | None = None) -> int:
+    """Number of covariance parameters: (sigma2, rho, tau2), (sigma2,
+    rho_space, rho_time, tau2), or (sigma2, rho_1..rho_d, tau2)."""
+    if family == FAMILY_ANISO:
+        if d is None:
+            raise ValueError("the anisotropic family needs the dimension d")
+        return d + 2
     return {FAMILY_ISO: 3, FAMILY_SPACETIME: 4}[family]
 
 
@@ -113,7 +120,7 @@ def cov_matrix(locs, covparms, family=FAMILY_ISO, nu=0.5, nspace=0):
     if locs.ndim == 1:
         locs = locs[:, None]
     k, d = locs.shape
-    P = nparms(family)
+    P = nparms(family, d)
     cp = np.ascontiguousarray(covparms, dtype=np.float64)
     S = np.empty((k, k))
     dS = np.empty((P, k, k))
@@ -145,7 +152,7 @@ def raw_sums(locs, NN, y, X, covparms, family=FAMILY_ISO, nu=0.5, nspace=0, i0=0
         X = X[:, None]
     p = X.shape[1]
     cp = np.ascontiguousarray(covparms, dtype=np.float64)
-    P = nparms(family)
+    P = nparms(family, d)
     if cp.shape != (P,):
         raise ValueError(f"covparms must have {P} entries")
     i1 = n if i1 is None else i1
@@ -283,7 +290,8 @@ def loglik_grad_info(locs, NN, y, X, covparms, family=FAMILY_ISO, nu=0.5, nspace
     if X.ndim == 1:
         X = X[:, None]
     raw = raw_sums(locs, NN, y, X, covparms, family, nu, nspace, threads=threads)
-    return combine(raw, len(y), X.shape[1], nparms(family))
+    d = 1 if np.ndim(locs) == 1 else np.shape(locs)[1]
+    return combine(raw, len(y), X.shape[1], nparms(family, d))
 
 
 def fisher_step(covparms, grad, info, max_step: float = 1.0):

@@ -48,6 +48,9 @@
  *   family 1, space-time:  (sigma2, rho_space, rho_time, tau2)     P = 4
  *     the first nspace coordinates are scaled by rho_space, the rest by
  *     rho_time:  h^2 = |dz_space|^2/rho_space^2 + |dz_time|^2/rho_time^2.
+ *   family 2, anisotropic: (sigma2, rho_1, ..., rho_d, tau2)      P = d + 2
+ *     one range per coordinate (Section 4.3, Eq. 6):
+ *     h^2 = sum_k (dz_k / rho_k)^2.
  *   Cov(a,b) = sigma2 * (f_nu(h) + tau2 * [a == b]),  h = scaled distance,
  *   f_0.5(h) = exp(-h), f_1.5(h) = (1+h) exp(-h),
  *   f_2.5(h) = (1 + h + h^2/3) exp(-h).
@@ -68,10 +71,13 @@
 
 #define OR_FAMILY_ISO 0
 #define OR_FAMILY_SPACETIME 1
+#define OR_FAMILY_ANISO 2
+#define OR_MAXP 40 /* most covariance parameters of any family */
 
-int oracle_nparms(int family) {
+int oracle_nparms(int family, int d) {
   if (family == OR_FAMILY_ISO) return 3;
   if (family == OR_FAMILY_SPACETIME) return 4;
+  if (family == OR_FAMILY_ANISO && d >= 1 && d <= OR_MAXP - 2) return d + 2;
   return -1;
 }
 
@@ -103,27 +109,31 @@ static int matern(double nu, double h, double* f, double* fp) {
  * and b are the same observation (the nugget applies). */
 static int cov_pair(int family, double nu, int nspace, int d, const double* covparms,
                     const double* za, const double* zb, int same, double* c, double* dc) {
-  int P = oracle_nparms(family);
+  int P = oracle_nparms(family, d);
   double sigma2 = covparms[0];
   double tau2 = covparms[P - 1];
-  double hg2[2] = {0.0, 0.0};
-  double rho[2];
-  int ngroups = (family == OR_FAMILY_ISO) ? 1 : 2;
-  rho[0] = covparms[1];
-  rho[1] = (family == OR_FAMILY_SPACETIME) ? covparms[2] : covparms[1];
+  /* range groups: one (isotropic), space and time, or one per coordinate;
+   * hg2[g] = squared scaled distance over the coordinates of group g */
+  int ngroups = P - 2;
+  double hg2[OR_MAXP];
+  for (int g = 0; g < ngroups; ++g) hg2[g] = 0.0;
   for (int k = 0; k < d; ++k) {
-    int g = (family == OR_FAMILY_SPACETIME && k >= nspace) ? 1 : 0;
-    double t = (za[k] - zb[k]) / rho[g];
+    int g = (family == OR_FAMILY_ISO) ? 0
+            : (family == OR_FAMILY_SPACETIME) ? (k >= nspace ? 1 : 0)
+                                               : k;
+    double t = (za[k] - zb[k]) / covparms[1 + g];
     hg2[g] += t * t;
   }
-  double h = sqrt(hg2[0] + hg2[1]);
+  double hh = 0.0;
+  for (int g = 0; g < ngroups; ++g) hh += hg2[g];
+  double h = sqrt(hh);
   double f, fp;
   if (matern(nu, h, &f, &fp) != OR_OK) return OR_EINVAL;
   *c = sigma2 * (f + (same ? tau2 : 0.0));
   dc[0] = f + (same ? tau2 : 0.0);
   for (int g = 0; g < ngroups; ++g) {
     /* dh/drho_g = -hg2 / (rho_g h), taken as 0 at h = 0 */
-    double dh = (h > 0.0) ? -hg2[g] / (rho[g] * h) : 0.0;
+    double dh = (h > 0.0) ? -hg2[g] / (covparms[1 + g] * h) : 0.0;
     dc[1 + g] = sigma2 * fp * dh;
   }
   dc[P - 1] = same ? sigma2 : 0.0;
@@ -134,9 +144,9 @@ static int cov_pair(int family, double nu, int nspace, int d, const double* covp
  * dS[P][k][k]; every index is its own observation. */
 int oracle_cov_matrix(int k, int d, const double* locs, int family, double nu, int nspace,
                       const double* covparms, double* S, double* dS) {
-  int P = oracle_nparms(family);
+  int P = oracle_nparms(family, d);
   if (P < 0 || k < 0 || d < 1) return OR_EINVAL;
-  double dc[8];
+  double dc[OR_MAXP];
   for (int a = 0; a < k; ++a) {
     for (int b = 0; b < k; ++b) {
       int st = cov_pair(family, nu, nspace, d, covparms, locs + (size_t)a * d,
@@ -206,7 +216,7 @@ int oracle_raw_sums(int64_t n, int m, int d, int p, int family, double nu, int n
                     const double* locs, const int32_t* NN, const double* y, const double* X,
                     const double* covparms, int64_t i0, int64_t i1, double* raw,
                     int64_t* bad_i) {
-  int P = oracle_nparms(family);
+  int P = oracle_nparms(family, d);
   *bad_i = -1;
   if (P < 0 || n < 1 || m < 0 || d < 1 || p < 1 || i0 < 0 || i1 > n || i0 > i1)
     return OR_EINVAL;
@@ -227,7 +237,7 @@ int oracle_raw_sums(int64_t n, int m, int d, int p, int family, double nu, int n
   double* deX = (double*)malloc(sizeof(double) * (size_t)(P * p));
   double* dv = (double*)malloc(sizeof(double) * (size_t)P);
   double* dey = (double*)malloc(sizeof(double) * (size_t)P);
-  double dcpair[8];
+  double dcpair[OR_MAXP];
   int status = OR_OK;
 
   for (int64_t i = i0; i < i1; ++i) {
@@ -259,7 +269,7 @@ int oracle_raw_sums(int64_t n, int m, int d, int p, int family, double nu, int n
       cov_pair(family, nu, nspace, d, covparms, za, zi, 0, &cvec[a], dcpair);
       for (int j = 0; j < P; ++j) dcvec[j * q + a] = dcpair[j];
     }
-    double sii, dsii[8];
+    double sii, dsii[OR_MAXP];
     cov_pair(family, nu, nspace, d, covparms, zi, zi, 1, &sii, dsii);
 
     /* kriging weights b, conditional variance v, residuals */

@@ -30,7 +30,14 @@ from scipy.special import gamma, kv
 import oracle
 from paper_2407_02740_amd import synthetic as S
 
-ISO, ST = oracle.FAMILY_ISO, oracle.FAMILY_SPACETIME
+ISO, ST, AN = oracle.FAMILY_ISO, oracle.FAMILY_SPACETIME, oracle.FAMILY_ANISO
+# coordinates of the anisotropic cases, and their ranges
+D_AN = 5
+RHO_AN = (0.35, 0.8, 0.2, 1.5, 0.5)
+
+
+def _dim(family):
+    return {ISO: 2, ST: 3, AN: D_AN}[family]
 
 
 def _problem(n, m, d=2, p=1, family=ISO, nu=0.5, seed=0, covparms=None, nspace=0):
@@ -41,7 +48,8 @@ def _problem(n, m, d=2, p=1, family=ISO, nu=0.5, seed=0, covparms=None, nspace=0
     y = rng.standard_normal(n)
     X = np.column_stack([np.ones(n)] + [rng.standard_normal(n) for _ in range(p - 1)])
     if covparms is None:
-        covparms = (1.3, 0.2, 0.05) if family == ISO else (1.1, 0.3, 0.4, 0.08)
+        covparms = {ISO: (1.3, 0.2, 0.05), ST: (1.1, 0.3, 0.4, 0.08),
+                    AN: (1.2,) + RHO_AN[:d] + (0.06,)}[family]
     return locs, NN, y, X, np.array(covparms, dtype=float)
 
 
@@ -79,12 +87,33 @@ def test_spacetime_reduces_to_isotropic_when_ranges_equal():
     np.testing.assert_allclose(dS1[1] + dS1[2], dS2[1], rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("family,nu", [(ISO, 0.5), (ISO, 1.5), (ISO, 2.5), (ST, 0.5), (ST, 2.5)])
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_anisotropic_is_isotropic_on_rescaled_coordinates(nu):
+    # Eq. 6 with a range per coordinate: dividing coordinate k by rho_k
+    # turns it into the unit-range isotropic covariance
+    rng = np.random.default_rng(21)
+    locs = rng.random((14, D_AN))
+    rho = np.array(RHO_AN)
+    S1, dS1 = oracle.cov_matrix(locs, (1.4,) + RHO_AN + (0.3,), AN, nu)
+    S2, dS2 = oracle.cov_matrix(locs / rho, (1.4, 1.0, 0.3), ISO, nu)
+    np.testing.assert_allclose(S1, S2, rtol=1e-14)
+    np.testing.assert_allclose(dS1[0], dS2[0], rtol=1e-14)
+    np.testing.assert_allclose(dS1[-1], dS2[-1], rtol=1e-14)
+    # equal ranges: the range derivatives add up to the isotropic one
+    S3, dS3 = oracle.cov_matrix(locs, (1.4,) + (0.6,) * D_AN + (0.3,), AN, nu)
+    S4, dS4 = oracle.cov_matrix(locs, (1.4, 0.6, 0.3), ISO, nu)
+    np.testing.assert_allclose(S3, S4, rtol=1e-14)
+    np.testing.assert_allclose(dS3[1:-1].sum(0), dS4[1], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("family,nu", [(ISO, 0.5), (ISO, 1.5), (ISO, 2.5), (ST, 0.5), (ST, 2.5),
+                                       (AN, 0.5), (AN, 1.5)])
 def test_cov_derivatives_match_finite_differences(family, nu):
     rng = np.random.default_rng(3)
-    d = 2 if family == ISO else 3
+    d = _dim(family)
     locs = rng.random((9, d))
-    cp = np.array((1.3, 0.25, 0.1)) if family == ISO else np.array((1.3, 0.25, 0.6, 0.1))
+    cp = np.array({ISO: (1.3, 0.25, 0.1), ST: (1.3, 0.25, 0.6, 0.1),
+                   AN: (1.3,) + RHO_AN + (0.1,)}[family])
     _, dS = oracle.cov_matrix(locs, cp, family, nu, nspace=2)
     for j in range(len(cp)):
         h = 1e-6 * cp[j]
@@ -114,10 +143,10 @@ def _dense_exact(locs, y, X, cp, family, nu, nspace=0):
 
 
 @pytest.mark.parametrize("family,nu,p", [(ISO, 0.5, 1), (ISO, 1.5, 3), (ISO, 2.5, 2), (ST, 0.5, 1),
-                                         (ST, 1.5, 2)])
+                                         (ST, 1.5, 2), (AN, 0.5, 1), (AN, 2.5, 2)])
 def test_full_conditioning_equals_dense_exact_gp(family, nu, p):
     n = 40
-    d = 2 if family == ISO else 3
+    d = _dim(family)
     locs, _, y, X, cp = _problem(n, 5, d=d, p=p, family=family, nu=nu, seed=4)
     NN = _full_nn(n)
     res = oracle.loglik_grad_info(locs, NN, y, X, cp, family, nu, nspace=2)
@@ -167,9 +196,10 @@ def _joint_minus_marginal(locs, NN, y, X, cp, family, nu, nspace=0):
 
 
 @pytest.mark.parametrize("family,nu,p,m", [(ISO, 0.5, 1, 4), (ISO, 1.5, 3, 6), (ISO, 2.5, 2, 3),
-                                           (ST, 0.5, 1, 5), (ST, 2.5, 2, 7)])
+                                           (ST, 0.5, 1, 5), (ST, 2.5, 2, 7), (AN, 0.5, 1, 6),
+                                           (AN, 1.5, 2, 4)])
 def test_every_sum_equals_joint_minus_marginal(family, nu, p, m):
-    d = 2 if family == ISO else 3
+    d = _dim(family)
     locs, NN, y, X, cp = _problem(60, m, d=d, p=p, family=family, nu=nu, seed=5)
     raw = oracle.raw_sums(locs, NN, y, X, cp, family, nu, nspace=2)
     got = oracle.unpack_raw(raw, p, len(cp))
@@ -282,9 +312,9 @@ def test_sigma2_identities(family, nu):
 
 
 @pytest.mark.parametrize("family,nu,p", [(ISO, 0.5, 1), (ISO, 1.5, 3), (ISO, 2.5, 1), (ST, 0.5, 1),
-                                         (ST, 2.5, 2)])
+                                         (ST, 2.5, 2), (AN, 0.5, 1)])
 def test_gradient_matches_finite_differences(family, nu, p):
-    d = 2 if family == ISO else 3
+    d = _dim(family)
     locs, NN, y, X, cp = _problem(400, 12, d=d, p=p, family=family, nu=nu, seed=9)
     res = oracle.loglik_grad_info(locs, NN, y, X, cp, family, nu, nspace=2)
     scale = np.sqrt(np.diag(res["info"]))
@@ -474,6 +504,47 @@ def test_invariances():
                            ainfo=0).items():
         np.testing.assert_allclose(r1[key], c ** power * np.asarray(r0[key]), rtol=1e-10,
                                    atol=1e-9, err_msg=key)
+
+
+def test_anisotropic_sums_reduce_and_transform():
+    n, m, p = 300, 8, 2
+    locs, NN, y, X, cp = _problem(n, m, d=D_AN, p=p, family=AN, nu=0.5, seed=12)
+    P = D_AN + 2
+    # equal ranges: the isotropic sums, the range entries adding up (chain rule)
+    eq = np.array((1.2,) + (0.45,) * D_AN + (0.06,))
+    a = oracle.unpack_raw(oracle.raw_sums(locs, NN, y, X, eq, AN, 0.5), p, P)
+    b = oracle.unpack_raw(oracle.raw_sums(locs, NN, y, X, (1.2, 0.45, 0.06), ISO, 0.5), p, 3)
+    collapse = np.zeros((3, P))
+    collapse[0, 0] = collapse[2, P - 1] = 1.0
+    collapse[1, 1:P - 1] = 1.0
+    for key in ("logdet", "ySy", "XSX", "ySX"):
+        np.testing.assert_allclose(a[key], b[key], rtol=1e-12, err_msg=key)
+    for key in ("dlogdet", "dySy", "dXSX", "dySX"):
+        got = np.tensordot(collapse, np.asarray(a[key]), axes=(1, 0))
+        np.testing.assert_allclose(got, b[key], rtol=1e-10, atol=1e-10, err_msg=key)
+    np.testing.assert_allclose(collapse @ a["ainfo"] @ collapse.T, b["ainfo"], rtol=1e-10)
+    # permuting the coordinates together with their ranges permutes the entries
+    base = oracle.unpack_raw(oracle.raw_sums(locs, NN, y, X, cp, AN, 0.5), p, P)
+    perm = np.array([3, 0, 4, 2, 1])
+    cpp = np.concatenate([[cp[0]], cp[1:-1][perm], [cp[-1]]])
+    got = oracle.unpack_raw(oracle.raw_sums(locs[:, perm], NN, y, X, cpp, AN, 0.5), p, P)
+    idx = np.concatenate([[0], 1 + perm, [P - 1]])
+    for key in ("dlogdet", "dySy", "dXSX", "dySX"):
+        np.testing.assert_allclose(got[key], np.asarray(base[key])[idx], rtol=1e-12, err_msg=key)
+    np.testing.assert_allclose(got["ainfo"], base["ainfo"][np.ix_(idx, idx)], rtol=1e-12)
+    # stretching coordinate k and rho_k by c: range-k entries scale by 1/c
+    k, c = 2, 3.0
+    st = locs.copy()
+    st[:, k] *= c
+    cps = cp.copy()
+    cps[1 + k] *= c
+    got = oracle.unpack_raw(oracle.raw_sums(st, NN, y, X, cps, AN, 0.5), p, P)
+    w = np.ones(P)
+    w[1 + k] = 1.0 / c
+    for key in ("dlogdet", "dySy", "dXSX", "dySX"):
+        ref = np.asarray(base[key]) * w.reshape((P,) + (1,) * (np.ndim(base[key]) - 1))
+        np.testing.assert_allclose(got[key], ref, rtol=1e-11, atol=1e-11, err_msg=key)
+    np.testing.assert_allclose(got["ainfo"], base["ainfo"] * np.outer(w, w), rtol=1e-11)
 
 
 def test_errors_are_reported_with_the_first_bad_observation():
