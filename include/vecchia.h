@@ -218,6 +218,23 @@ size_t vec_ordered_nn_workspace_bytes(int64_t n, int32_t d, int32_t m);
 int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t* NNarray,
                    void* workspace, size_t workspace_bytes, void* stream);
 
+/* Coarse-to-fine ordering of locs[n][d] (d = 1, 2 or 3), an approximation of
+ * the maxmin ordering that Section 2.1 builds the conditioning sets on.
+ * Coordinates are quantised to a 2^B grid over the bounding box,
+ * B = min(max(1, ceil(log2(max(n, 2)) / d)), floor(60 / d)); the cell code
+ * interleaves the grid bits (most significant first, coordinate 0 first
+ * within a level) and is read bit-reversed, so coarse lattices come before
+ * the finer ones between them.  Points of one cell are ranked by tie[] (any
+ * finite doubles, e.g. uniform draws; equal ties by input index), and the
+ * order is that of (rank in cell, reversed code, tie, index).
+ * order[n] (int64) receives the input index of each position; locs_out
+ * (may be NULL; must not alias locs) receives the reordered points.
+ * workspace: vec_maxmin_order_workspace_bytes(n, d) bytes (0 if the
+ * arguments are invalid or the device cannot be queried). */
+size_t vec_maxmin_order_workspace_bytes(int64_t n, int32_t d);
+int vec_maxmin_order(int64_t n, int32_t d, const double* locs, const double* tie, int64_t* order,
+                     double* locs_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* The combine step of vec_loglik on sums assembled by the caller:
  * raw_sum = raw_a + raw_b (raw_b may be NULL; 2 + p*p + p doubles each,
  * e.g. the parts of the observations evaluated by two different paths),

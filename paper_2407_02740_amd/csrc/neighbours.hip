@@ -17,6 +17,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "point_box.hpp"
 #include "vecchia.h"
 
 namespace vecchia_nn {
@@ -37,45 +38,6 @@ struct Grid {
 __device__ __forceinline__ int cell_coord(double x, double lo, double side, int g) {
   int c = (int)floor((x - lo) / side);
   return c < 0 ? 0 : (c >= g ? g - 1 : c);
-}
-
-template <int D>
-__global__ void bbox_kernel(int64_t n, const double* __restrict__ locs, double* __restrict__ box) {
-  __shared__ double lo[256][D], hi[256][D];
-  double l[D], h[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    l[k] = INFINITY;
-    h[k] = -INFINITY;
-  }
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double x = locs[i * D + k];
-      l[k] = fmin(l[k], x);
-      h[k] = fmax(h[k], x);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    lo[threadIdx.x][k] = l[k];
-    hi[threadIdx.x][k] = h[k];
-  }
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        lo[threadIdx.x][k] = fmin(lo[threadIdx.x][k], lo[threadIdx.x + w][k]);
-        hi[threadIdx.x][k] = fmax(hi[threadIdx.x][k], hi[threadIdx.x + w][k]);
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < D) {
-    box[threadIdx.x] = lo[0][threadIdx.x];
-    box[D + threadIdx.x] = hi[0][threadIdx.x];
-  }
 }
 
 __global__ void zero_i32_kernel(int32_t* __restrict__ x, int64_t count) {
@@ -323,7 +285,7 @@ Grid make_grid(const double* lo, const double* hi, int d, int64_t b1) {
 
 template <int D>
 int run(int64_t n, int m, const double* locs, int32_t* NN, const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(bbox_kernel<D>, dim3(1), dim3(256), 0, st, n, locs, w.box);
+  hipLaunchKernelGGL(vecchia_box::bbox_kernel<D>, dim3(1), dim3(256), 0, st, n, locs, w.box);
   double box[2 * kMaxD];
   if (hipMemcpyAsync(box, w.box, 2 * D * sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||

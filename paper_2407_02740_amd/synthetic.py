@@ -68,13 +68,14 @@ def maxmin_exact(locs: np.ndarray) -> np.ndarray:
     return order
 
 
-def maxmin_approx(locs: np.ndarray, seed: int = 0) -> np.ndarray:
+def maxmin_approx(locs: np.ndarray, seed: int = 0, tie: np.ndarray | None = None) -> np.ndarray:
     """Approximate maxmin ordering by bit-reversed Morton codes.
 
     Coordinates are quantised to a 2^B grid per dimension (B chosen so a cell
     holds about one point); the interleaved cell code is bit-reversed so that
     coarse lattices come first and finer ones fill in between (coarse to
-    fine); ties are broken at random.
+    fine); points of a cell are ranked by ``tie`` (uniform draws from
+    ``seed`` unless given; equal ties by input index).
     """
     n, d = locs.shape
     rng = np.random.default_rng(seed)
@@ -94,7 +95,8 @@ def maxmin_approx(locs: np.ndarray, seed: int = 0) -> np.ndarray:
     rev = np.zeros(n, dtype=np.int64)
     for b in range(B * d):
         rev |= ((code >> b) & 1) << (B * d - 1 - b)
-    tie = rng.random(n)
+    if tie is None:
+        tie = rng.random(n)
     # several points can share a cell: a cell's k-th point comes after every
     # cell's (k-1)-th point, so each pass over the cells is coarse to fine
     by_cell = np.lexsort((tie, rev))

@@ -89,6 +89,11 @@ def lib():
         L.vec_ordered_nn.restype = ctypes.c_int
         L.vec_ordered_nn.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
                                      ctypes.c_size_t, _VP]
+        L.vec_maxmin_order_workspace_bytes.restype = ctypes.c_size_t
+        L.vec_maxmin_order_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+        L.vec_maxmin_order.restype = ctypes.c_int
+        L.vec_maxmin_order.argtypes = [ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
+                                       ctypes.c_size_t, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
         L.vec_fisher_fit.restype = ctypes.c_int
@@ -340,6 +345,29 @@ def ordered_nn(locs, m: int, device: str = "cuda") -> torch.Tensor:
     _check(lib().vec_ordered_nn(n, d, m, x.data_ptr(), NN.data_ptr(), ws.data_ptr(), nb,
                                 _stream()), "vec_ordered_nn")
     return NN
+
+
+def maxmin_order(locs, tie, device: str = "cuda"):
+    """(order, reordered locs) of the points locs ([n][d], d <= 3) by the
+    library's coarse-to-fine ordering (vec_maxmin_order); tie [n] breaks the
+    order within a grid cell.  order is int64 on the device."""
+    x = torch.as_tensor(locs, dtype=torch.float64).to(device).contiguous()
+    if x.dim() == 1:
+        x = x[:, None].contiguous()
+    n, d = x.shape
+    t = torch.as_tensor(tie, dtype=torch.float64).to(x.device).contiguous()
+    if t.shape != (n,):
+        raise ValueError("tie must hold one value per point")
+    nb = lib().vec_maxmin_order_workspace_bytes(n, d)
+    if nb == 0:
+        raise VecchiaError(VEC_EINVAL, "vec_maxmin_order_workspace_bytes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+    order = torch.empty(n, dtype=torch.int64, device=x.device)
+    out = torch.empty_like(x)
+    _check(lib().vec_maxmin_order(n, d, x.data_ptr(), t.data_ptr(), order.data_ptr(),
+                                  out.data_ptr(), ws.data_ptr(), nb, _stream()),
+           "vec_maxmin_order")
+    return order, out
 
 
 class Predictor:

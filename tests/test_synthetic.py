@@ -30,6 +30,43 @@ def test_maxmin_approx_is_a_coarse_to_fine_permutation():
     assert d_first.min() > 2 * d_rand.min()
 
 
+def _coarse_to_fine_by_definition(locs, tie):
+    """The ordering written out point by point: grid cell, bit-reversed
+    interleaved code, rank in the cell by (tie, index), then one Python sort
+    of (rank, code, tie, index) tuples."""
+    n, d = locs.shape
+    B = min(max(1, int(np.ceil(np.log2(max(n, 2)) / d))), 60 // d)
+    lo, hi = locs.min(0), locs.max(0)
+    keys = []
+    for i in range(n):
+        bits = []
+        for b in range(B - 1, -1, -1):
+            for k in range(d):
+                span = max(hi[k] - lo[k], 1e-300)
+                c = min(int((locs[i, k] - lo[k]) / span * 2 ** B), 2 ** B - 1)
+                bits.append((c >> b) & 1)
+        # bit-reversed: the first interleaved bit is the least significant
+        rev = sum(bit << j for j, bit in enumerate(bits))
+        keys.append((rev, tie[i], i))
+    by_cell = sorted(keys)
+    rank = {}
+    for pos, (rev, t, i) in enumerate(by_cell):
+        rank[i] = 0 if pos == 0 or by_cell[pos - 1][0] != rev else rank[by_cell[pos - 1][2]] + 1
+    return np.array([i for _, _, _, i in sorted((rank[i], r, t, i) for r, t, i in keys)])
+
+
+def test_maxmin_approx_follows_its_definition():
+    rng = np.random.default_rng(7)
+    for n, d in [(1, 2), (2, 1), (300, 1), (500, 2), (700, 3)]:
+        locs = rng.random((n, d))
+        tie = rng.random(n)
+        assert np.array_equal(S.maxmin_approx(locs, tie=tie), _coarse_to_fine_by_definition(locs, tie))
+    # clustered points (many per cell), repeated ties and a zero-extent axis
+    locs = np.column_stack([rng.integers(0, 4, 400) / 4.0, np.zeros(400)])
+    tie = rng.integers(0, 3, 400).astype(float)
+    assert np.array_equal(S.maxmin_approx(locs, tie=tie), _coarse_to_fine_by_definition(locs, tie))
+
+
 def test_ordered_nn_matches_brute_force():
     rng = np.random.default_rng(2)
     for d in (2, 4):
