@@ -21,7 +21,8 @@
  *   hipStream_t passed as void*, NULL = the default stream) and outputs are
  *   valid once the stream has reached that point.
  * Layouts (row-major, no padding):
- *   locs[n][d]        FP64 coordinates (1 <= d <= 4).
+ *   locs[n][d]        FP64 coordinates (1 <= d <= 4; up to 32 for
+ *                     VEC_FAMILY_ANISO).
  *   NNarray[n][m+1]   int32, 0-based.  Row i holds i in column 0 and its
  *                     q = min(i, m) conditioning neighbours in columns 1..q,
  *                     each a previous observation (0 <= j < i), in any order;
@@ -30,9 +31,11 @@
  *   covparms[P]       FP64 covariance parameters, read on the device:
  *                       VEC_FAMILY_ISO        (sigma2, rho, tau2)          P = 3
  *                       VEC_FAMILY_SPACETIME  (sigma2, rho_s, rho_t, tau2) P = 4
+ *                       VEC_FAMILY_ANISO      (sigma2, rho_1..rho_d, tau2) P = d + 2
  *                     Cov(a, b) = sigma2 * (f_nu(h) + tau2 * [a == b]) with
  *                     h the range-scaled distance (space-time: the first
- *                     nspace coordinates scaled by rho_s, the rest by rho_t),
+ *                     nspace coordinates scaled by rho_s, the rest by rho_t;
+ *                     anisotropic: coordinate k scaled by rho_k),
  *                     f_0.5 = e^-h, f_1.5 = (1+h) e^-h,
  *                     f_2.5 = (1 + h + h^2/3) e^-h  (Section 4.3, Eq. 6 at
  *                     nu = 0.5; tau2 is the nugget-to-variance ratio).
@@ -80,13 +83,19 @@ extern "C" {
 
 #define VEC_FAMILY_ISO 0
 #define VEC_FAMILY_SPACETIME 1
+/* One range per coordinate, for the higher-dimensional inputs of Section 4
+ * (Eq. 6 with rho_1..rho_d): d <= 32, m <= 63.  It runs on a kernel that
+ * gives every neighbourhood a whole wave; vec_raw_sums, vec_block_sums,
+ * vec_combine, vecchia_loglik_grad_info, vec_fisher_update and
+ * vec_fisher_fit accept it, the other entry points return VEC_EINVAL. */
+#define VEC_FAMILY_ANISO 2
 
 typedef struct {
   int64_t n;         /* number of observations (n >= 1, n < 2^31)          */
   int32_t m;         /* neighbours per observation: NNarray has m+1 columns */
-  int32_t d;         /* coordinates per location, 1..4                     */
+  int32_t d;         /* coordinates per location, 1..4 (ANISO: 1..32)      */
   int32_t p;         /* covariates (columns of X), 1..3                    */
-  int32_t family;    /* VEC_FAMILY_ISO or VEC_FAMILY_SPACETIME             */
+  int32_t family;    /* VEC_FAMILY_ISO, _SPACETIME or _ANISO               */
   double smoothness; /* Matern smoothness nu: 0.5, 1.5 or 2.5 (fixed)      */
   int32_t nspace;    /* space-time: leading spatial coordinates, 1..d-1    */
   int32_t reserved;  /* must be 0                                          */
@@ -98,7 +107,8 @@ int vec_nparms(const vec_problem* pb);
 int vec_nraw(const vec_problem* pb);
 int vec_nout(const vec_problem* pb);
 
-/* Largest m the library accepts. */
+/* Largest m the library accepts for the isotropic and space-time families
+ * (VEC_FAMILY_ANISO accepts m <= 63). */
 int vec_max_m(void);
 
 /* Bytes of device workspace vec_raw_sums needs for the observation range

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "vecchia.h"
+#include "vecchia_aniso.hpp"
 #include "vecchia_kernels.hpp"
 
 namespace vecchia {
@@ -57,22 +58,30 @@ static const resident_fn kResidentBatch[kNumK][3][2] = {
 // count at K <= 31, so a second round of workgroups fills in behind the first).
 constexpr int kBlocksPerCU = VECCHIA_BLOCKS_PER_CU;
 constexpr int kMaxP = 3;
-constexpr int kMaxParms = 4;
+constexpr int kMaxParms = 4;                            // fused-kernel families
+constexpr int kMaxParmsAniso = vecchia_aniso::kMaxD + 2;  // one range per coordinate
 
 struct Dims {
   int p, P, nraw, nout, kidx, nu;
+  bool aniso;  // VEC_FAMILY_ANISO: the wave-per-neighbourhood kernel
 };
 
 static bool dims_of(const vec_problem* pb, Dims* dm) {
   if (!pb) return false;
   if (pb->n < 1 || pb->n >= (int64_t)INT32_MAX) return false;
-  if (pb->m < 0 || pb->d < 1 || pb->d > 4 || pb->p < 1 || pb->p > kMaxP) return false;
+  if (pb->m < 0 || pb->d < 1 || pb->p < 1 || pb->p > kMaxP) return false;
   if (pb->reserved != 0) return false;
+  dm->aniso = false;
   if (pb->family == VEC_FAMILY_ISO) {
+    if (pb->d > 4) return false;
     dm->P = 3;
   } else if (pb->family == VEC_FAMILY_SPACETIME) {
-    if (pb->nspace < 1 || pb->nspace >= pb->d) return false;
+    if (pb->d > 4 || pb->nspace < 1 || pb->nspace >= pb->d) return false;
     dm->P = 4;
+  } else if (pb->family == VEC_FAMILY_ANISO) {
+    if (pb->d > vecchia_aniso::kMaxD || pb->m + 1 > vecchia_aniso::kMaxK) return false;
+    dm->P = pb->d + 2;
+    dm->aniso = true;
   } else {
     return false;
   }
@@ -91,7 +100,7 @@ static bool dims_of(const vec_problem* pb, Dims* dm) {
       break;
     }
   }
-  if (dm->kidx < 0) return false;
+  if (dm->kidx < 0 && !dm->aniso) return false;
   dm->p = pb->p;
   dm->nraw = nraw_of(dm->p, dm->P);
   dm->nout = 1 + dm->P + dm->P * dm->P + dm->p + dm->p * dm->p;
@@ -250,13 +259,14 @@ __global__ void combine_kernel(int64_t n, int p, int P, const double* __restrict
   if (threadIdx.x == 0) combine_one(n, p, P, raw, out, status);
 }
 
-// Eq. (4) on the log scale with a step-length cap.
+// Eq. (4) on the log scale with a step-length cap (P <= MAXP).
+template <int MAXP>
 __device__ void fisher_one(int P, const double* __restrict__ out, double* __restrict__ covparms,
                            int32_t* __restrict__ status, double max_step) {
   if (status[0] != 0) return;
   const double* grad = out + 1;
   const double* info = grad + P;
-  double th[kMaxParms], g[kMaxParms], I[kMaxParms * kMaxParms];
+  double th[MAXP], g[MAXP], I[MAXP * MAXP];
   for (int j = 0; j < P; ++j) {
     th[j] = covparms[j];
     g[j] = th[j] * grad[j];
@@ -275,10 +285,21 @@ __device__ void fisher_one(int P, const double* __restrict__ out, double* __rest
   for (int j = 0; j < P; ++j) covparms[j] = th[j] * exp(g[j] * scale);
 }
 
+template <int MAXP>
 __global__ void fisher_kernel(int P, const double* __restrict__ out,
                               double* __restrict__ covparms, int32_t* __restrict__ status,
                               double max_step) {
-  if (threadIdx.x == 0) fisher_one(P, out, covparms, status, max_step);
+  if (threadIdx.x == 0) fisher_one<MAXP>(P, out, covparms, status, max_step);
+}
+
+static void enqueue_fisher(const Dims& dm, const double* out, double* covparms, int32_t* status,
+                           double max_step, hipStream_t st) {
+  if (dm.P <= kMaxParms)
+    hipLaunchKernelGGL(fisher_kernel<kMaxParms>, dim3(1), dim3(64), 0, st, dm.P, out, covparms,
+                       status, max_step);
+  else
+    hipLaunchKernelGGL(fisher_kernel<kMaxParmsAniso>, dim3(1), dim3(64), 0, st, dm.P, out,
+                       covparms, status, max_step);
 }
 
 // ----------------------------------------------------------------------------
@@ -320,7 +341,8 @@ __global__ void batch_fisher_kernel(int nsets, int P, int nout, const double* __
                                     double max_step) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nsets)
-    fisher_one(P, out + (int64_t)b * nout, covparms + (int64_t)b * P, status + 2 * b, max_step);
+    fisher_one<kMaxParms>(P, out + (int64_t)b * nout, covparms + (int64_t)b * P, status + 2 * b,
+                          max_step);
 }
 
 __global__ void fill_u32_kernel(unsigned int* __restrict__ x, int count, unsigned int v) {
@@ -364,6 +386,30 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
                               double* partials, size_t partials_bytes, int* grid_out,
                               int32_t* status, hipStream_t st, double* rows_out = nullptr,
                               const int32_t* index = nullptr, int64_t nn_row0 = 0) {
+  if (dm.aniso) {
+    // the sums of Algorithm 1 with their derivatives and information only
+    if (mode != kModeSums || rows_out || index || nn_row0 != 0) return VEC_EINVAL;
+    const int grid = vecchia_aniso::aniso_grid(i1 - i0);
+    *grid_out = grid;
+    if (grid == 0) return VEC_OK;
+    if (!partials || partials_bytes < (size_t)grid * dm.nraw * sizeof(double))
+      return VEC_EWORKSPACE;
+    vecchia_aniso::AnisoArgs args = {};
+    args.m = pb->m;
+    args.d = pb->d;
+    args.p = dm.p;
+    args.nu = dm.nu;
+    args.locs = locs;
+    args.NN = NN;
+    args.y = y;
+    args.X = X;
+    args.covparms = covparms;
+    args.i0 = i0;
+    args.i1 = i1;
+    args.partials = partials;
+    args.status = status;
+    return hip_code(vecchia_aniso::launch_aniso(args, grid, st));
+  }
   const int grid = grid_for(i1 - i0);
   *grid_out = grid;
   if (grid == 0) return VEC_OK;
@@ -451,7 +497,7 @@ static bool batch_dims(const vec_batch* bt, Dims* dm) {
   pb.family = bt->family;
   pb.smoothness = 0.5;
   pb.nspace = bt->nspace;
-  return dims_of(&pb, dm);
+  return dims_of(&pb, dm) && !dm->aniso;
 }
 
 static int nu_code(double smoothness) {
@@ -545,7 +591,7 @@ int vec_max_m(void) { return kKs[kNumK - 1] - 1; }
 size_t vec_workspace_bytes(const vec_problem* pb, int64_t i0, int64_t i1) {
   Dims dm;
   if (!dims_of(pb, &dm) || i0 < 0 || i1 < i0 || i1 > pb->n) return 0;
-  const int grid = grid_for(i1 - i0);
+  const int grid = dm.aniso ? vecchia_aniso::aniso_grid(i1 - i0) : grid_for(i1 - i0);
   return (size_t)(grid > 0 ? grid : 1) * dm.nraw * sizeof(double);
 }
 
@@ -652,7 +698,7 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
 
 size_t vec_kriging_predict_workspace_bytes(const vec_problem* pb, int64_t n_obs) {
   Dims dm;
-  if (!dims_of(pb, &dm) || n_obs < pb->m || n_obs >= pb->n) return 0;
+  if (!dims_of(pb, &dm) || dm.aniso || n_obs < pb->m || n_obs >= pb->n) return 0;
   const int64_t n_pred = pb->n - n_obs;
   return align256(vec_workspace_bytes(pb, n_obs, pb->n)) +
          align256((size_t)n_pred * (pb->m + 1) * sizeof(double)) +
@@ -664,7 +710,7 @@ int vec_kriging_predict(const vec_problem* pb, const double* locs, const int32_t
                         const double* betahat, int64_t n_obs, double* mean, double* var,
                         void* workspace, size_t workspace_bytes, int32_t* status, void* stream) {
   Dims dm;
-  if (!dims_of(pb, &dm) || n_obs < pb->m || n_obs >= pb->n) return VEC_EINVAL;
+  if (!dims_of(pb, &dm) || dm.aniso || n_obs < pb->m || n_obs >= pb->n) return VEC_EINVAL;
   if (!locs || !NN_pred || !y || !X || !covparms || !betahat || !mean || !var || !status)
     return VEC_EINVAL;
   const size_t need = vec_kriging_predict_workspace_bytes(pb, n_obs);
@@ -711,8 +757,7 @@ int vec_fisher_update(const vec_problem* pb, const double* out, double* covparms
                       int32_t* status, double max_step, void* stream) {
   Dims dm;
   if (!dims_of(pb, &dm) || !out || !covparms || !status || !(max_step > 0.0)) return VEC_EINVAL;
-  hipLaunchKernelGGL(fisher_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), dm.P,
-                     out, covparms, status, max_step);
+  enqueue_fisher(dm, out, covparms, status, max_step, static_cast<hipStream_t>(stream));
   return hip_code(hipGetLastError());
 }
 
@@ -740,8 +785,7 @@ static int one_iteration(const vec_problem* pb, const Dims& dm, const double* lo
                         wsb, status, st);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, dm.P, raw, out, status);
-  hipLaunchKernelGGL(fisher_kernel, dim3(1), dim3(64), 0, st, dm.P, out, covparms, status,
-                     max_step);
+  enqueue_fisher(dm, out, covparms, status, max_step, st);
   return hip_code(hipGetLastError());
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvecchia.
 
 VEC_OK, VEC_EINVAL, VEC_ENOTPD, VEC_EBADNN, VEC_ENONFINITE, VEC_EHIP, VEC_EWORKSPACE = \
     0, -1, -2, -3, -4, -5, -6
-FAMILY_ISO, FAMILY_SPACETIME = 0, 1
+FAMILY_ISO, FAMILY_SPACETIME, FAMILY_ANISO = 0, 1, 2
 ERRORS = {VEC_EINVAL: "invalid argument", VEC_ENOTPD: "covariance not positive definite",
           VEC_EBADNN: "malformed NNarray row", VEC_ENONFINITE: "non-finite value",
           VEC_EHIP: "HIP runtime error", VEC_EWORKSPACE: "workspace too small"}
@@ -124,7 +124,11 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
-def nparms(family: int) -> int:
+def nparms(family: int, d: int | None = None) -> int:
+    if family == FAMILY_ANISO:
+        if d is None:
+            raise ValueError("the anisotropic family needs the dimension d")
+        return d + 2
     return {FAMILY_ISO: 3, FAMILY_SPACETIME: 4}[family]
 
 

@@ -51,6 +51,18 @@ def test_problem_sizes_and_validation_on_host():
         pbx = V.Problem(**{k: v for k, v in args.items() if k != "reserved"})
         pbx.reserved = args.get("reserved", 0)
         assert L.vec_nparms(ctypes.byref(pbx)) == V.VEC_EINVAL, change
+    # one range per coordinate: P = d + 2 up to d = 32, m up to 63
+    pa = V.Problem(n=15000, m=30, d=18, p=1, family=V.FAMILY_ANISO, smoothness=0.5, nspace=0)
+    assert L.vec_nparms(ctypes.byref(pa)) == 20
+    assert L.vec_nraw(ctypes.byref(pa)) == 2 + 1 + 1 + 20 * 4 + 400
+    for change in [dict(d=33), dict(m=64), dict(p=4), dict(smoothness=2.0), dict(d=0)]:
+        args = dict(n=15000, m=30, d=18, p=1, family=V.FAMILY_ANISO, smoothness=0.5, nspace=0)
+        args.update(change)
+        assert L.vec_nparms(ctypes.byref(V.Problem(**args))) == V.VEC_EINVAL, change
+    for ok in [dict(d=32, m=63, p=3), dict(d=1, m=0)]:
+        args = dict(n=15000, m=30, d=18, p=1, family=V.FAMILY_ANISO, smoothness=1.5, nspace=0)
+        args.update(ok)
+        assert L.vec_nparms(ctypes.byref(V.Problem(**args))) == args["d"] + 2, ok
     # null pointers and bad ranges are rejected before anything is enqueued
     null = None
     rc = L.vec_raw_sums(ctypes.byref(pb), null, null, null, null, null, 0, 1000, null, null, 0,
@@ -105,7 +117,8 @@ def test_batch_plan_validation_on_host():
 
     bad = [
         dict(bt_kw=dict(nsets=0)), dict(bt_kw=dict(d=5)), dict(bt_kw=dict(p=0)),
-        dict(bt_kw=dict(family=3)), dict(bt_kw=dict(reserved=1)), dict(bt_kw=dict(n_total=299)),
+        dict(bt_kw=dict(family=3)), dict(bt_kw=dict(family=V.FAMILY_ANISO)),
+        dict(bt_kw=dict(reserved=1)), dict(bt_kw=dict(n_total=299)),
         dict(bt_kw=dict(nn_total=1100 + 200 * 41 - 1)),
         dict(sets={0: dict(n=0)}), dict(sets={0: dict(m=-1)}), dict(sets={1: dict(m=41)}),
         dict(sets={0: dict(smoothness=1.0)}), dict(sets={0: dict(reserved=2)}),
