@@ -26,6 +26,11 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
   kriging_weights pinned: the loglik sums rebuilt from its weights and
                 variances equal raw_sums' (a different code path, C, Neumaier
                 sums); b = 0 and v = 1 + tau2 when the neighbours are far.
+  grouped_raw_sums  (grouped.py) pinned: blocks of one observation equal
+                raw_sums (the C code, a different implementation); one block
+                of everything, and two blocks with full conditioning, equal the
+                dense exact GP; every block equals the joint-minus-marginal
+                dense expression; finite differences of the log-likelihood.
   fisher_step   pinned: the Eq. (4) update is a fixed point at the MLE of the
                 AR(1) closed form (scipy optimiser).
 """
@@ -49,3 +54,4 @@ from .oracle import (  # noqa: F401
     raw_sums,
     unpack_raw,
 )
+from .grouped import grouped_raw_sums  # noqa: E402,F401

@@ -162,6 +162,85 @@ def find_ordered_nn(locs: np.ndarray, m: int, workers: int = -1, log=None) -> np
     return NN
 
 
+def group_cells(locs: np.ndarray, g: int, m: int, seed: int = 0):
+    """Blocks of at most g nearby points and their conditioning sets, for
+    grouped Vecchia.  Points are binned on a grid with about g points per
+    cell (a cell with more is split into chunks of g); blocks are ordered
+    coarse to fine by their centroids (the bit-reversed Morton ordering);
+    block b's conditioning set is the m points before it, in the new order,
+    nearest to any of its members (ties by index).
+
+    Returns (order, block_start, cond_start, cond): order[k] is the input
+    index of the k-th reordered point, block b holds reordered points
+    [block_start[b], block_start[b + 1]), and cond[cond_start[b]:
+    cond_start[b + 1]] (int32, indices into the reordered points, each below
+    block_start[b]) is its conditioning set, nearest first."""
+    from scipy.spatial import cKDTree
+
+    n, d = locs.shape
+    lo = locs.min(0)
+    span = np.maximum(locs.max(0) - lo, 1e-300)
+    per = max(1, int(round((n / g) ** (1.0 / d))))
+    cell = np.minimum(((locs - lo) / span * per).astype(np.int64), per - 1)
+    key = np.zeros(n, dtype=np.int64)
+    for k in range(d):
+        key = key * per + cell[:, k]
+    by = np.argsort(key, kind="stable")
+    ks = key[by]
+    starts = np.r_[0, np.flatnonzero(np.diff(ks)) + 1, n]
+    blocks = []
+    for a, b in zip(starts[:-1], starts[1:]):
+        for c in range(a, b, g):
+            blocks.append(by[c:min(b, c + g)])
+    cent = np.array([locs[bl].mean(0) for bl in blocks])
+    border = maxmin_approx(cent, seed)
+    order = np.concatenate([blocks[j] for j in border])
+    sizes = np.array([len(blocks[j]) for j in border])
+    block_start = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    pts = locs[order]
+    nb = len(sizes)
+    member_block = np.repeat(np.arange(nb), sizes)
+    bstart_of = block_start[member_block]
+    cond_lists = [None] * nb
+    # doubling chunks of the reordered points: a tree on [0, hi) serves the
+    # blocks that start in [lo_, hi)
+    lo_ = 0
+    first = 0
+    while first < nb:
+        hi = max(2 * max(lo_, 1), int(block_start[first + 1]))
+        last = int(np.searchsorted(block_start, hi, side="left")) - 1
+        last = min(max(last, first), nb - 1)
+        hi = int(block_start[last + 1])
+        tree = cKDTree(pts[:hi])
+        mem = np.arange(block_start[first], hi)
+        kq = min(hi, m + g + 8)
+        while True:
+            dist, idx = tree.query(pts[mem], k=kq)
+            if kq == 1:
+                dist, idx = dist[:, None], idx[:, None]
+            valid = idx < bstart_of[mem][:, None]
+            need = np.minimum(m, bstart_of[mem])
+            if np.all(valid.sum(1) >= need) or kq >= hi:
+                break
+            kq = min(hi, 2 * kq)
+        for bb in range(first, last + 1):
+            sl = slice(block_start[bb] - block_start[first], block_start[bb + 1] - block_start[first])
+            dd, ii = dist[sl][valid[sl]], idx[sl][valid[sl]]
+            if len(ii) == 0:
+                cond_lists[bb] = np.zeros(0, dtype=np.int64)
+                continue
+            o = np.lexsort((ii, dd))
+            ii = ii[o]
+            _, keep = np.unique(ii, return_index=True)
+            ii = ii[np.sort(keep)][:m]
+            cond_lists[bb] = ii
+        lo_ = hi
+        first = last + 1
+    cond_start = np.r_[0, np.cumsum([len(c) for c in cond_lists])].astype(np.int64)
+    cond = np.concatenate(cond_lists).astype(np.int32) if nb else np.zeros(0, np.int32)
+    return order, block_start, cond_start, cond
+
+
 # ----------------------------------------------------------------------------
 # responses
 # ----------------------------------------------------------------------------
