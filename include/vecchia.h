@@ -84,7 +84,7 @@ extern "C" {
 #define VEC_FAMILY_ISO 0
 #define VEC_FAMILY_SPACETIME 1
 /* One range per coordinate, for the higher-dimensional inputs of Section 4
- * (Eq. 6 with rho_1..rho_d): d <= 32, m <= 63.  It runs on a kernel that
+ * (Eq. 6 with rho_1..rho_d): d <= 32, m <= 63.  It runs on the kernel that
  * gives every neighbourhood a whole wave; vec_raw_sums, vec_block_sums,
  * vec_combine, vecchia_loglik_grad_info, vec_fisher_update and
  * vec_fisher_fit accept it, the other entry points return VEC_EINVAL. */
@@ -107,8 +107,12 @@ int vec_nparms(const vec_problem* pb);
 int vec_nraw(const vec_problem* pb);
 int vec_nout(const vec_problem* pb);
 
-/* Largest m the library accepts for the isotropic and space-time families
- * (VEC_FAMILY_ANISO accepts m <= 63). */
+/* Largest m that every entry point accepts (40): the batched calls and the
+ * loglik-only, adjoint, kriging-weights and prediction passes stop there.
+ * vec_raw_sums, vec_block_sums, vecchia_loglik_grad_info and the Fisher
+ * calls accept m <= 63 for every family; neighbourhoods of more than 41
+ * observations (and VEC_FAMILY_ANISO) run on a kernel that gives each
+ * neighbourhood a whole wave. */
 int vec_max_m(void);
 
 /* Bytes of device workspace vec_raw_sums needs for the observation range
@@ -241,6 +245,44 @@ int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t*
  * (may be NULL; must not alias locs) receives the reordered points.
  * workspace: vec_maxmin_order_workspace_bytes(n, d) bytes (0 if the
  * arguments are invalid or the device cannot be queried). */
+/* Grouped Vecchia (Section 2.1: conditioning on the joint distribution of
+ * several observations at once): the ordered observations 0..n-1 are split
+ * into consecutive blocks, block b = [block_start[b], block_start[b + 1])
+ * of 1..max_block observations, and each block's conditioning set is
+ * cond[cond_start[b] .. cond_start[b + 1]), at most pb->m earlier
+ * observations (each index < block_start[b]; any order).  The likelihood is
+ * the product of the block conditionals p(y_B | y_N), and the raw sums are
+ * those of vec_raw_sums with every term taken for the block as a whole:
+ *   logdet += log det V,  ySy += e_y' V^-1 e_y, ... (V the conditional
+ *   covariance of the block, e its conditional residuals),
+ *   ainfo   = the expected information of the block conditionals,
+ * so vec_combine and vec_fisher_update apply unchanged; blocks of one
+ * observation with cond = the NNarray rows give vec_raw_sums.
+ * block_start[nblocks + 1], cond_start[nblocks + 1] (int64) and
+ * cond[ncond] (int32) are device arrays; pb->NNarray conventions do not
+ * apply.  Limits: max_block <= 8, pb->m + max_block <= 64, d <= 4 when
+ * max_block > 1, 1 + p + (P - 1) max_block <= 64.  A block that breaks
+ * them, or an index out of range, sets VEC_FLAG_BADNN with the block's
+ * first observation.  workspace: vec_grouped_workspace_bytes(pb, nblocks). */
+size_t vec_grouped_workspace_bytes(const vec_problem* pb, int64_t nblocks);
+int vec_grouped_raw_sums(const vec_problem* pb, const double* locs, const double* y,
+                         const double* X, const double* covparms, int64_t nblocks,
+                         const int64_t* block_start, const int64_t* cond_start,
+                         const int32_t* cond, int64_t ncond, int32_t max_block, double* raw,
+                         void* workspace, size_t workspace_bytes, int32_t* status, void* stream);
+
+/* Fisher scoring (Eq. 4) on the grouped likelihood: `iters` iterations of
+ * grouped sums, combine and update on covparms (device, in place); with
+ * use_graph != 0 and a non-NULL stream one iteration is captured as a HIP
+ * graph and replayed.  raw, out as for vec_fisher_fit. */
+int vec_grouped_fisher_fit(const vec_problem* pb, const double* locs, const double* y,
+                           const double* X, double* covparms, int64_t nblocks,
+                           const int64_t* block_start, const int64_t* cond_start,
+                           const int32_t* cond, int64_t ncond, int32_t max_block, int32_t iters,
+                           double max_step, double* raw, double* out, void* workspace,
+                           size_t workspace_bytes, int32_t* status, int32_t use_graph,
+                           void* stream);
+
 size_t vec_maxmin_order_workspace_bytes(int64_t n, int32_t d);
 int vec_maxmin_order(int64_t n, int32_t d, const double* locs, const double* tie, int64_t* order,
                      double* locs_out, void* workspace, size_t workspace_bytes, void* stream);

@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "vecchia.h"
-#include "vecchia_aniso.hpp"
+#include "vecchia_wave.hpp"
 #include "vecchia_kernels.hpp"
 
 namespace vecchia {
@@ -59,11 +59,11 @@ static const resident_fn kResidentBatch[kNumK][3][2] = {
 constexpr int kBlocksPerCU = VECCHIA_BLOCKS_PER_CU;
 constexpr int kMaxP = 3;
 constexpr int kMaxParms = 4;                            // fused-kernel families
-constexpr int kMaxParmsAniso = vecchia_aniso::kMaxD + 2;  // one range per coordinate
+constexpr int kMaxParmsAniso = vecchia_wave::kMaxD + 2;  // one range per coordinate
 
 struct Dims {
   int p, P, nraw, nout, kidx, nu;
-  bool aniso;  // VEC_FAMILY_ANISO: the wave-per-neighbourhood kernel
+  bool wave;  // the wave-per-neighbourhood kernel (one range per coordinate, or m + 1 > 41)
 };
 
 static bool dims_of(const vec_problem* pb, Dims* dm) {
@@ -71,7 +71,7 @@ static bool dims_of(const vec_problem* pb, Dims* dm) {
   if (pb->n < 1 || pb->n >= (int64_t)INT32_MAX) return false;
   if (pb->m < 0 || pb->d < 1 || pb->p < 1 || pb->p > kMaxP) return false;
   if (pb->reserved != 0) return false;
-  dm->aniso = false;
+  dm->wave = false;
   if (pb->family == VEC_FAMILY_ISO) {
     if (pb->d > 4) return false;
     dm->P = 3;
@@ -79,9 +79,9 @@ static bool dims_of(const vec_problem* pb, Dims* dm) {
     if (pb->d > 4 || pb->nspace < 1 || pb->nspace >= pb->d) return false;
     dm->P = 4;
   } else if (pb->family == VEC_FAMILY_ANISO) {
-    if (pb->d > vecchia_aniso::kMaxD || pb->m + 1 > vecchia_aniso::kMaxK) return false;
+    if (pb->d > vecchia_wave::kMaxD || pb->m + 1 > vecchia_wave::kMaxK) return false;
     dm->P = pb->d + 2;
-    dm->aniso = true;
+    dm->wave = true;
   } else {
     return false;
   }
@@ -100,7 +100,11 @@ static bool dims_of(const vec_problem* pb, Dims* dm) {
       break;
     }
   }
-  if (dm->kidx < 0 && !dm->aniso) return false;
+  if (dm->kidx < 0) {
+    // neighbourhoods beyond the fused kernel's sizes: the wave kernel
+    if (pb->m + 1 > vecchia_wave::kMaxK) return false;
+    dm->wave = true;
+  }
   dm->p = pb->p;
   dm->nraw = nraw_of(dm->p, dm->P);
   dm->nout = 1 + dm->P + dm->P * dm->P + dm->p + dm->p * dm->p;
@@ -292,14 +296,138 @@ __global__ void fisher_kernel(int P, const double* __restrict__ out,
   if (threadIdx.x == 0) fisher_one<MAXP>(P, out, covparms, status, max_step);
 }
 
+// The same update for many parameters, spread over one 64-lane workgroup:
+// the scaled information in LDS, a right-looking Cholesky with the rows of
+// each column step split over the lanes, and column-sweep substitutions.
+template <int MAXP>
+__global__ __launch_bounds__(64) void fisher_wide_kernel(int P, const double* __restrict__ out,
+                                                         double* __restrict__ covparms,
+                                                         int32_t* __restrict__ status,
+                                                         double max_step) {
+  __shared__ double I[MAXP][MAXP + 1];
+  __shared__ double g[MAXP], th[MAXP];
+  __shared__ int fail;
+  const int t = threadIdx.x;
+  if (status[0] != 0) return;  // the same word for every lane
+  const double* grad = out + 1;
+  const double* info = grad + P;
+  if (t == 0) fail = 0;
+  for (int j = t; j < P; j += 64) {
+    th[j] = covparms[j];
+    g[j] = th[j] * grad[j];
+  }
+  __syncthreads();
+  for (int e = t; e < P * P; e += 64) {
+    const int j = e / P, k = e % P;
+    I[j][k] = th[j] * info[e] * th[k];
+  }
+  __syncthreads();
+  for (int c = 0; c < P; ++c) {
+    if (t == 0) {
+      const double piv = I[c][c];
+      if (!(piv > 0.0)) fail = 1;
+      I[c][c] = sqrt(piv);
+    }
+    __syncthreads();
+    if (fail) break;  // the same value for every lane
+    for (int r = c + 1 + t; r < P; r += 64) I[r][c] /= I[c][c];
+    __syncthreads();
+    const int w = P - c - 1;
+    for (int e = t; e < w * w; e += 64) {
+      const int r = c + 1 + e / w, s2 = c + 1 + e % w;
+      if (s2 <= r) I[r][s2] -= I[r][c] * I[s2][c];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (t == 0) atomicOr(&status[0], VEC_FLAG_NONFINITE);
+    return;
+  }
+  for (int c = 0; c < P; ++c) {  // L y = g
+    if (t == 0) g[c] /= I[c][c];
+    __syncthreads();
+    for (int r = c + 1 + t; r < P; r += 64) g[r] -= I[r][c] * g[c];
+    __syncthreads();
+  }
+  for (int c = P - 1; c >= 0; --c) {  // L^T x = y
+    if (t == 0) g[c] /= I[c][c];
+    __syncthreads();
+    for (int r = t; r < c; r += 64) g[r] -= I[c][r] * g[c];
+    __syncthreads();
+  }
+  double norm2 = 0.0;
+  for (int j = 0; j < P; ++j) norm2 += g[j] * g[j];
+  const double norm = sqrt(norm2);
+  const double scale = (norm > max_step) ? max_step / norm : 1.0;
+  for (int j = t; j < P; j += 64) covparms[j] = th[j] * exp(g[j] * scale);
+}
+
+// The combine step spread over one workgroup (many parameters): the GLS
+// solve and the log-likelihood on lane 0, gradient entries and copies of the
+// information over the lanes.
+__global__ __launch_bounds__(64) void combine_wide_kernel(int64_t n, int p, int P,
+                                                          const double* __restrict__ raw,
+                                                          double* __restrict__ out,
+                                                          int32_t* __restrict__ status) {
+  __shared__ double beta[kMaxP];
+  __shared__ int ok;
+  const int t = threadIdx.x;
+  const double logdet = raw[0], ySy = raw[1];
+  const double* XSX = raw + 2;
+  const double* ySX = XSX + p * p;
+  const double* dlogdet = ySX + p;
+  const double* dySy = dlogdet + P;
+  const double* dXSX = dySy + P;
+  const double* dySX = dXSX + P * p * p;
+  const double* ainfo = dySX + P * p;
+  if (t == 0) {
+    double L[kMaxP * kMaxP], b[kMaxP];
+    for (int e = 0; e < p * p; ++e) L[e] = XSX[e];
+    for (int j = 0; j < p; ++j) b[j] = ySX[j];
+    ok = small_chol(L, p) ? 1 : 0;
+    if (ok) small_chol_solve(L, p, b);
+    double quad = ySy;
+    for (int j = 0; j < p; ++j) {
+      quad -= ySX[j] * b[j];
+      beta[j] = b[j];
+    }
+    out[0] = -0.5 * ((double)n * log(2.0 * M_PI) + logdet + quad);
+  }
+  __syncthreads();
+  bool finite = true;
+  for (int j = t; j < P; j += 64) {
+    double gj = dlogdet[j] + dySy[j];
+    for (int a = 0; a < p; ++a) gj -= 2.0 * beta[a] * dySX[j * p + a];
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) gj += beta[a] * dXSX[(j * p + a) * p + b] * beta[b];
+    out[1 + j] = -0.5 * gj;
+    finite = finite && __builtin_isfinite(gj);
+  }
+  for (int e = t; e < P * P; e += 64) out[1 + P + e] = ainfo[e];
+  for (int j = t; j < p; j += 64) out[1 + P + P * P + j] = beta[j];
+  for (int e = t; e < p * p; e += 64) out[1 + P + P * P + p + e] = XSX[e];
+  if (t == 0) finite = finite && ok && __builtin_isfinite(out[0]);
+  if (!finite) atomicOr(&status[0], VEC_FLAG_NONFINITE);
+}
+
 static void enqueue_fisher(const Dims& dm, const double* out, double* covparms, int32_t* status,
                            double max_step, hipStream_t st) {
   if (dm.P <= kMaxParms)
     hipLaunchKernelGGL(fisher_kernel<kMaxParms>, dim3(1), dim3(64), 0, st, dm.P, out, covparms,
                        status, max_step);
   else
-    hipLaunchKernelGGL(fisher_kernel<kMaxParmsAniso>, dim3(1), dim3(64), 0, st, dm.P, out,
+    hipLaunchKernelGGL(fisher_wide_kernel<kMaxParmsAniso>, dim3(1), dim3(64), 0, st, dm.P, out,
                        covparms, status, max_step);
+}
+
+static void enqueue_combine(const vec_problem* pb, const Dims& dm, const double* raw, double* out,
+                            int32_t* status, hipStream_t st) {
+  if (dm.P <= kMaxParms)
+    hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, dm.P, raw, out,
+                       status);
+  else
+    hipLaunchKernelGGL(combine_wide_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, dm.P, raw, out,
+                       status);
 }
 
 // ----------------------------------------------------------------------------
@@ -386,17 +514,20 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
                               double* partials, size_t partials_bytes, int* grid_out,
                               int32_t* status, hipStream_t st, double* rows_out = nullptr,
                               const int32_t* index = nullptr, int64_t nn_row0 = 0) {
-  if (dm.aniso) {
+  if (dm.wave) {
     // the sums of Algorithm 1 with their derivatives and information only
     if (mode != kModeSums || rows_out || index || nn_row0 != 0) return VEC_EINVAL;
-    const int grid = vecchia_aniso::aniso_grid(i1 - i0);
+    const int grid = vecchia_wave::wave_grid(i1 - i0);
     *grid_out = grid;
     if (grid == 0) return VEC_OK;
     if (!partials || partials_bytes < (size_t)grid * dm.nraw * sizeof(double))
       return VEC_EWORKSPACE;
-    vecchia_aniso::AnisoArgs args = {};
+    vecchia_wave::WaveArgs args = {};
     args.m = pb->m;
     args.d = pb->d;
+    args.family = pb->family;
+    args.nspace = pb->nspace;
+    args.R = dm.P - 2;
     args.p = dm.p;
     args.nu = dm.nu;
     args.locs = locs;
@@ -408,7 +539,7 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
     args.i1 = i1;
     args.partials = partials;
     args.status = status;
-    return hip_code(vecchia_aniso::launch_aniso(args, grid, st));
+    return hip_code(vecchia_wave::launch_wave(args, grid, st));
   }
   const int grid = grid_for(i1 - i0);
   *grid_out = grid;
@@ -497,7 +628,7 @@ static bool batch_dims(const vec_batch* bt, Dims* dm) {
   pb.family = bt->family;
   pb.smoothness = 0.5;
   pb.nspace = bt->nspace;
-  return dims_of(&pb, dm) && !dm->aniso;
+  return dims_of(&pb, dm) && !dm->wave;
 }
 
 static int nu_code(double smoothness) {
@@ -565,6 +696,56 @@ static int check_batch_call(const vec_batch* bt, const vec_batch_plan* plan, con
   return VEC_OK;
 }
 
+// Grouped sums: one wave per block, then the fixed-order reduction.
+static int check_grouped(const vec_problem* pb, const Dims& dm, int64_t nblocks, int32_t max_block) {
+  if (nblocks < 0 || max_block < 1 || max_block > vecchia_wave::kMaxBlock) return VEC_EINVAL;
+  if (max_block > 1 && pb->d > 4) return VEC_EINVAL;
+  if (pb->m + max_block > vecchia_wave::kMaxK) return VEC_EINVAL;
+  if (1 + dm.p + (dm.P - 1) * max_block > 64) return VEC_EINVAL;  // solved columns
+  return VEC_OK;
+}
+
+static int enqueue_grouped_sums(const vec_problem* pb, const Dims& dm, const double* locs,
+                                const double* y, const double* X, const double* covparms,
+                                int64_t nblocks, const int64_t* block_start,
+                                const int64_t* cond_start, const int32_t* cond, int64_t ncond,
+                                int32_t max_block, double* raw, void* workspace,
+                                size_t workspace_bytes, int32_t* status, hipStream_t st) {
+  if (nblocks == 0) {
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, raw, dm.nraw, 0.0);
+    return hip_code(hipGetLastError());
+  }
+  const int grid = vecchia_wave::wave_grid(nblocks);
+  if (!workspace || workspace_bytes < (size_t)grid * dm.nraw * sizeof(double))
+    return VEC_EWORKSPACE;
+  vecchia_wave::WaveArgs args = {};
+  args.m = pb->m;
+  args.d = pb->d;
+  args.p = dm.p;
+  args.nu = dm.nu;
+  args.family = pb->family;
+  args.nspace = pb->nspace;
+  args.R = dm.P - 2;
+  args.locs = locs;
+  args.y = y;
+  args.X = X;
+  args.covparms = covparms;
+  args.i0 = 0;
+  args.i1 = nblocks;
+  args.block_start = block_start;
+  args.cond_start = cond_start;
+  args.cond = cond;
+  args.ncond = ncond;
+  args.gmax = max_block;
+  args.n = pb->n;
+  args.partials = static_cast<double*>(workspace);
+  args.status = status;
+  if (vecchia_wave::launch_wave(args, grid, st) != hipSuccess) return VEC_EHIP;
+  hipLaunchKernelGGL(reduce_kernel, dim3(dm.nraw), dim3(256), 0, st, args.partials, grid, dm.nraw,
+                     raw);
+  return hip_code(hipGetLastError());
+}
+
 }  // namespace vecchia
 
 using namespace vecchia;
@@ -591,7 +772,7 @@ int vec_max_m(void) { return kKs[kNumK - 1] - 1; }
 size_t vec_workspace_bytes(const vec_problem* pb, int64_t i0, int64_t i1) {
   Dims dm;
   if (!dims_of(pb, &dm) || i0 < 0 || i1 < i0 || i1 > pb->n) return 0;
-  const int grid = dm.aniso ? vecchia_aniso::aniso_grid(i1 - i0) : grid_for(i1 - i0);
+  const int grid = dm.wave ? vecchia_wave::wave_grid(i1 - i0) : grid_for(i1 - i0);
   return (size_t)(grid > 0 ? grid : 1) * dm.nraw * sizeof(double);
 }
 
@@ -627,8 +808,7 @@ int vec_combine(const vec_problem* pb, const double* raw, double* out, int32_t* 
                 void* stream) {
   Dims dm;
   if (!dims_of(pb, &dm) || !raw || !out || !status) return VEC_EINVAL;
-  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), pb->n,
-                     dm.p, dm.P, raw, out, status);
+  enqueue_combine(pb, dm, raw, out, status, static_cast<hipStream_t>(stream));
   return hip_code(hipGetLastError());
 }
 
@@ -698,7 +878,7 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
 
 size_t vec_kriging_predict_workspace_bytes(const vec_problem* pb, int64_t n_obs) {
   Dims dm;
-  if (!dims_of(pb, &dm) || dm.aniso || n_obs < pb->m || n_obs >= pb->n) return 0;
+  if (!dims_of(pb, &dm) || dm.wave || n_obs < pb->m || n_obs >= pb->n) return 0;
   const int64_t n_pred = pb->n - n_obs;
   return align256(vec_workspace_bytes(pb, n_obs, pb->n)) +
          align256((size_t)n_pred * (pb->m + 1) * sizeof(double)) +
@@ -710,7 +890,7 @@ int vec_kriging_predict(const vec_problem* pb, const double* locs, const int32_t
                         const double* betahat, int64_t n_obs, double* mean, double* var,
                         void* workspace, size_t workspace_bytes, int32_t* status, void* stream) {
   Dims dm;
-  if (!dims_of(pb, &dm) || dm.aniso || n_obs < pb->m || n_obs >= pb->n) return VEC_EINVAL;
+  if (!dims_of(pb, &dm) || dm.wave || n_obs < pb->m || n_obs >= pb->n) return VEC_EINVAL;
   if (!locs || !NN_pred || !y || !X || !covparms || !betahat || !mean || !var || !status)
     return VEC_EINVAL;
   const size_t need = vec_kriging_predict_workspace_bytes(pb, n_obs);
@@ -784,7 +964,7 @@ static int one_iteration(const vec_problem* pb, const Dims& dm, const double* lo
   int rc = enqueue_sums(pb, dm, kModeSums, locs, NN, y, X, covparms, nullptr, 0, pb->n, raw, ws,
                         wsb, status, st);
   if (rc != VEC_OK) return rc;
-  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, pb->n, dm.p, dm.P, raw, out, status);
+  enqueue_combine(pb, dm, raw, out, status, st);
   enqueue_fisher(dm, out, covparms, status, max_step, st);
   return hip_code(hipGetLastError());
 }
@@ -811,6 +991,77 @@ int vec_fisher_fit(const vec_problem* pb, const double* locs, const int32_t* NNa
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return VEC_EHIP;
   int rc = one_iteration(pb, dm, locs, NNarray, y, X, covparms, max_step, raw, out, workspace,
                          workspace_bytes, status, st);
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (rc != VEC_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != VEC_OK ? rc : VEC_EHIP;
+  }
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) {
+    for (int it = 0; it < iters && e == hipSuccess; ++it) e = hipGraphLaunch(exec, st);
+    (void)hipGraphExecDestroy(exec);
+  }
+  (void)hipGraphDestroy(graph);
+  return hip_code(e);
+}
+
+size_t vec_grouped_workspace_bytes(const vec_problem* pb, int64_t nblocks) {
+  Dims dm;
+  if (!dims_of(pb, &dm) || nblocks < 0) return 0;
+  const int grid = vecchia_wave::wave_grid(nblocks);
+  return (size_t)(grid > 0 ? grid : 1) * dm.nraw * sizeof(double);
+}
+
+int vec_grouped_raw_sums(const vec_problem* pb, const double* locs, const double* y,
+                         const double* X, const double* covparms, int64_t nblocks,
+                         const int64_t* block_start, const int64_t* cond_start,
+                         const int32_t* cond, int64_t ncond, int32_t max_block, double* raw,
+                         void* workspace, size_t workspace_bytes, int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm)) return VEC_EINVAL;
+  int rc = check_grouped(pb, dm, nblocks, max_block);
+  if (rc != VEC_OK) return rc;
+  if (!locs || !y || !X || !covparms || !raw || !status || ncond < 0) return VEC_EINVAL;
+  if (nblocks > 0 && (!block_start || !cond_start || (ncond > 0 && !cond))) return VEC_EINVAL;
+  return enqueue_grouped_sums(pb, dm, locs, y, X, covparms, nblocks, block_start, cond_start, cond,
+                              ncond, max_block, raw, workspace, workspace_bytes, status,
+                              static_cast<hipStream_t>(stream));
+}
+
+int vec_grouped_fisher_fit(const vec_problem* pb, const double* locs, const double* y,
+                           const double* X, double* covparms, int64_t nblocks,
+                           const int64_t* block_start, const int64_t* cond_start,
+                           const int32_t* cond, int64_t ncond, int32_t max_block, int32_t iters,
+                           double max_step, double* raw, double* out, void* workspace,
+                           size_t workspace_bytes, int32_t* status, int32_t use_graph,
+                           void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm) || iters < 0 || !(max_step > 0.0)) return VEC_EINVAL;
+  int rc = check_grouped(pb, dm, nblocks, max_block);
+  if (rc != VEC_OK) return rc;
+  if (!locs || !y || !X || !covparms || !raw || !out || !status || ncond < 0) return VEC_EINVAL;
+  if (nblocks > 0 && (!block_start || !cond_start || (ncond > 0 && !cond))) return VEC_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto one = [&]() -> int {
+    int r = enqueue_grouped_sums(pb, dm, locs, y, X, covparms, nblocks, block_start, cond_start,
+                                 cond, ncond, max_block, raw, workspace, workspace_bytes, status,
+                                 st);
+    if (r != VEC_OK) return r;
+    enqueue_combine(pb, dm, raw, out, status, st);
+    enqueue_fisher(dm, out, covparms, status, max_step, st);
+    return hip_code(hipGetLastError());
+  };
+  if (!use_graph || st == nullptr || iters == 0) {
+    for (int it = 0; it < iters; ++it) {
+      rc = one();
+      if (rc != VEC_OK) return rc;
+    }
+    return VEC_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return VEC_EHIP;
+  rc = one();
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc != VEC_OK || e != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);

@@ -1,38 +1,50 @@
-// Per-neighbourhood Vecchia sums for covariances with one range per
-// coordinate (Section 4.3, Eq. 6 with rho_1..rho_d; the high-dimensional
-// regression setting of Section 4.2), FP64, gfx950.
+// Wave-per-neighbourhood Vecchia sums, FP64, gfx950: the kernel for what the
+// 16-lane fused kernel does not hold in registers --
+//   * one range per coordinate (Section 4.3, Eq. 6 with rho_1..rho_d; the
+//     high-dimensional regression setting of Section 4.2): P = d + 2
+//     derivative directions and an O(P^2) information block;
+//   * neighbourhoods of more than 41 observations (m up to 63);
+//   * grouped Vecchia (Section 2.1): the conditional density of a block of
+//     g consecutive observations given a conditioning set of c earlier ones.
+// A single observation is a block of one whose conditioning set is its
+// NNarray row, so one code path serves all three.
 //
-// With P = d + 2 covariance parameters the per-neighbourhood state (P
-// derivative directions, a P x P information block, nraw = O(P^2) sums)
-// no longer fits the 16-lane register layout of the fused kernel, so this
-// kernel gives each neighbourhood a whole wave and keeps the matrices in
-// LDS.  A workgroup is one wave; it loops over observations i0 + blockIdx.x,
-// + gridDim.x, ... and keeps its sums in LDS (each lane owns the entries
-// e = lane (mod 64)), written once to partials[blockIdx.x][nraw] at the end.
+// A workgroup is one wave; it loops over blocks i0 + blockIdx.x,
+// + gridDim.x, ... and keeps its sums in LDS (lane l owns the entries
+// e = l (mod 64)), written once to partials[blockIdx.x][nraw] at the end.
 //
-// Steps per neighbourhood (local order: the q neighbours, then i last):
-//   gather      scaled coordinates z_k / rho_k, y, X into LDS.
-//   covariance  lower triangle of Sigma (pairs spread over the lanes); the
-//               upper triangle keeps the pair factor F_ab = -sigma2 f'(h)/h,
-//               so that dSigma_ab/drho_k = F_ab s_k^2 / rho_k with
-//               s_k = (z_ak - z_bk) / rho_k.
-//   Cholesky    right-looking, in place; trailing updates spread over lanes.
-//   u           u = L^-T e_q (back substitution, lanes = rows).
-//   g_k         g_k = dSigma/drho_k u for every range k: lanes = rows, the
-//               column loop split between the two half-waves at m + 1 <= 32.
-//   solves      L^-1 applied to y, X, g_1..g_d and u (one column per lane).
-//   Gram        G = V_<q' V_<q over all solved columns (pairs over lanes).
-//   sums        with w_j = L^-1 dSigma_j u (w_sigma2 = e_q / sigma2,
-//               w_tau2 = sigma2 L^-1 u), Sy_j, SX_j and G_jk from the Gram
-//               matrix, the self row adds the same terms as the fused kernel:
-//                 logdet += log L_qq^2, ySy += Liy_q^2, ...,
-//                 ainfo_jk += G_jk + w_j[q] w_k[q] / 2.
+// Per block, local order: the c conditioning observations, then the g block
+// members (k = c + g <= 64 rows):
+//   gather      scaled coordinates z / rho (zero-padded to DMAX), y, X.
+//   covariance  pairs spread over the lanes: Sigma transposed into the upper
+//               triangle of A, the pair factor F_ab = -sigma2 f'(h)/h into the
+//               lower one (dSigma_ab/drho = F_ab s^2 / rho, s the scaled
+//               coordinate difference of that range).
+//   Cholesky    Sigma = L L' in registers, lane r holding row r; column
+//               entries broadcast with readlane; L' written back to A.
+//   U           U = L^-T E_B, the block's g unit vectors (back substitution,
+//               lanes = rows, the g columns side by side).
+//   G_j         G_j = dSigma_j U for every range j (lanes = rows; the column
+//               loop split between the two half-waves when k <= 32).
+//   solves      L^-1 applied to y, X, every G_j and U (one column per lane).
+//   Gram        products of the solved columns over the conditioning rows.
+//   sums        with W_j = L^-1 dSigma_j U (W_sigma2 = E_B / sigma2,
+//               W_tau2 = sigma2 L^-1 U), z = L^-1 y, Z = L^-1 X and b, b'
+//               running over the block rows:
+//                 logdet   += sum_b log L_bb^2,  ySy += sum_b z_b^2, ...
+//                 dlogdet_j += sum_b W_j[b, b]
+//                 dySy_j   += -2 sum_b z_b (W_j' z)_<c,b - sum_bb' z_b W_j[b, b'] z_b'
+//                 ainfo_jk += sum_b (W_j' W_k)_<c,bb + 1/2 sum_bb' W_j[b, b'] W_k[b, b']
+//               (the differences between the joint terms over the
+//               neighbourhood and those over the conditioning set, in the
+//               factor's coordinates; one block row gives the fused kernel's
+//               single-observation terms).
 #include <math.h>
 
 #include "vecchia.h"
-#include "vecchia_aniso.hpp"
+#include "vecchia_wave.hpp"
 
-namespace vecchia_aniso {
+namespace vecchia_wave {
 namespace {
 
 constexpr int kLanes = 64;
@@ -40,16 +52,19 @@ constexpr int kLanes = 64;
 // Offsets (in doubles) of the per-workgroup LDS regions.
 struct Layout {
   int SA, SZ, SV, NR, P, nraw;
-  int oA, oZ, oV, oG, oAcc, oDinv, oInvRho, oTri, oIdx, total;
+  int oA, oZ, oV, oG, oAcc, oDinv, oInvRho, oTri, total;
 };
 
-__host__ __device__ inline Layout layout_of(int kmax, int d, int p) {
+// kmax: neighbourhood rows; dmax: coordinate slots per row (the slots
+// d..dmax-1 hold zeros); R range parameters; gmax: largest block.  NR is
+// the number of solved columns of the largest block.
+__host__ __device__ inline Layout layout_of(int kmax, int dmax, int R, int p, int gmax) {
   Layout L;
-  L.SA = kmax + 2;                    // rows of Sigma / L
-  L.SZ = (d % 2 == 0) ? d + 1 : d;    // rows of scaled coordinates (odd stride)
-  L.SV = kmax + 1;                    // solved columns
-  L.P = d + 2;
-  L.NR = 1 + p + d + 1;               // y, X, g_1..g_d, u
+  L.SA = kmax + 1;  // odd: column accesses by lane hit distinct banks
+  L.SZ = dmax + 2;  // even: rows start 16-byte aligned
+  L.SV = kmax + 1;
+  L.P = R + 2;
+  L.NR = 1 + p + (R + 1) * gmax;  // y, X, G_j (g columns each), U (g columns)
   L.nraw = 2 + p * p + p + L.P * (2 + p * p + p) + L.P * L.P;
   const int T = kmax > L.NR ? kmax : L.NR;  // largest triangle enumerated
   int o = 0;
@@ -69,11 +84,13 @@ __host__ __device__ inline Layout layout_of(int kmax, int d, int p) {
   o += kMaxD;
   L.oTri = o;
   o += (T * (T + 1) / 2 + 1) / 2;
-  L.oIdx = o;
-  o += (kmax + 1) / 2;
   L.total = o;
   return L;
 }
+
+// LDS operations of one wave complete in program order, and a workgroup is
+// one wave: ordering them needs only a compiler fence.
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
   const long long b = __double_as_longlong(x);
@@ -82,13 +99,31 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int KMAX, int DMAX>
-__global__ __launch_bounds__(kLanes) void aniso_kernel(const AnisoArgs a) {
+// 1/sqrt(x): hardware estimate y0 and one second-order Newton correction,
+// y = y0 (1 + e/2 + 3e^2/8) with e = 1 - x y0^2.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * y0), y0, 1.0);
+  return fma(y0 * e, fma(0.375, e, 0.5), y0);
+}
+
+__device__ __forceinline__ void flag(int32_t* status, int f, int64_t i) {
+  atomicOr(&status[0], f);
+  atomicMin(&status[1], (int32_t)i);
+}
+
+// A (KMAX x SA): Sigma transposed in the upper triangle (A[c][r] = Sigma_rc,
+// c <= r) until the factorisation, then L transposed there (A[c][r] =
+// L_rc); the strict lower triangle holds the pair factors (A[r][c] = F_rc).
+template <int KMAX, int DMAX, int GMAX>
+__global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x;
-  const int m = a.m, d = a.d, p = a.p, nu = a.nu;
-  const Layout Ly = layout_of(KMAX, d, p);
-  const int SA = Ly.SA, SZ = Ly.SZ, SV = Ly.SV, NR = Ly.NR, P = Ly.P, nraw = Ly.nraw;
+  const int m = a.m, d = a.d, p = a.p, nu = a.nu, R = a.R;
+  const bool per_coord = (a.family == VEC_FAMILY_ANISO);
+  const bool grouped = (a.block_start != nullptr);
+  const Layout Ly = layout_of(KMAX, DMAX, R, p, grouped ? a.gmax : 1);
+  const int SA = Ly.SA, SZ = Ly.SZ, SV = Ly.SV, P = Ly.P, nraw = Ly.nraw;
   double* __restrict__ A = lds + Ly.oA;
   double* __restrict__ Z = lds + Ly.oZ;
   double* __restrict__ V = lds + Ly.oV;
@@ -97,59 +132,84 @@ __global__ __launch_bounds__(kLanes) void aniso_kernel(const AnisoArgs a) {
   double* __restrict__ dinv = lds + Ly.oDinv;
   double* __restrict__ invrho = lds + Ly.oInvRho;
   int32_t* __restrict__ tri = reinterpret_cast<int32_t*>(lds + Ly.oTri);
-  int32_t* __restrict__ idx = reinterpret_cast<int32_t*>(lds + Ly.oIdx);
 
-  const double sigma2 = a.covparms[0], tau2 = a.covparms[d + 1];
-  // tri[r (r + 1) / 2 + c] = (r, c), c <= r: the pair enumeration of every
-  // triangle below (covariance pairs, trailing updates, Gram pairs)
-  const int T = KMAX > NR ? KMAX : NR;
+  const double sigma2 = a.covparms[0], tau2 = a.covparms[R + 1];
+  // range parameter of coordinate k
+  auto grp = [&](int k) {
+    return per_coord ? k : ((a.family == VEC_FAMILY_SPACETIME && k >= a.nspace) ? 1 : 0);
+  };
+  // tri[r (r + 1) / 2 + c] = (r, c), c <= r: the pair enumeration of the
+  // covariance pairs and of the Gram pairs
+  const int T = KMAX > Ly.NR ? KMAX : Ly.NR;
   for (int r = lane; r < T; r += kLanes)
     for (int c = 0; c <= r; ++c) tri[r * (r + 1) / 2 + c] = r | (c << 16);
-  for (int k = lane; k < d; k += kLanes) invrho[k] = 1.0 / a.covparms[1 + k];
+  for (int k = lane; k < kMaxD; k += kLanes) invrho[k] = (k < d) ? 1.0 / a.covparms[1 + grp(k)] : 0.0;
   for (int e = lane; e < nraw; e += kLanes) acc[e] = 0.0;
-  __syncthreads();
+  wave_fence();
 
-  for (int64_t i = a.i0 + blockIdx.x; i < a.i1; i += gridDim.x) {
-    const int q = (int)(i < m ? i : m), kk = q + 1;
-    const int32_t* row = a.NN + i * (int64_t)(m + 1);
+  for (int64_t u = a.i0 + blockIdx.x; u < a.i1; u += gridDim.x) {
+    // ---- the block: first member, size g, conditioning set (c entries)
+    int64_t first, cbase = 0;
+    int c, g;
+    const int32_t* row = nullptr;
+    if (grouped) {
+      first = a.block_start[u];
+      const int64_t last = a.block_start[u + 1];
+      cbase = a.cond_start[u];
+      const int64_t cend = a.cond_start[u + 1];
+      const bool ok = first >= 0 && last > first && last - first <= a.gmax && last <= a.n &&
+                      cbase >= 0 && cend >= cbase && cend <= a.ncond && cend - cbase <= m &&
+                      (cend - cbase) + (last - first) <= KMAX;
+      if (!ok) {  // the same values in every lane
+        if (lane == 0) flag(a.status, VEC_FLAG_BADNN, first > 0 ? first : 0);
+        continue;
+      }
+      g = (int)(last - first);
+      c = (int)(cend - cbase);
+    } else {
+      first = u;
+      g = 1;
+      c = (int)(u < m ? u : m);
+      row = a.NN + u * (int64_t)(m + 1);
+    }
+    const int kk = c + g;
     bool bad = false;
-    if (lane < q) {
-      const int32_t j = row[1 + lane];
-      bad = (j < 0 || (int64_t)j >= i);
-      idx[lane] = bad ? 0 : j;
-    } else if (lane == q) {
-      bad = (row[0] != (int32_t)i);
-      idx[q] = (int32_t)i;
+    int64_t src = first + (lane - c);
+    if (lane < c) {
+      const int32_t j = grouped ? a.cond[cbase + lane] : row[1 + lane];
+      bad = (j < 0 || (int64_t)j >= first);
+      src = bad ? 0 : j;
+    } else if (!grouped && lane == c) {
+      bad = (row[0] != (int32_t)u);
     }
     if (__ballot(bad) != 0ull) {
-      if (lane == 0) {
-        atomicOr(&a.status[0], VEC_FLAG_BADNN);
-        atomicMin(&a.status[1], (int32_t)i);
-      }
-      __syncthreads();
+      if (lane == 0) flag(a.status, VEC_FLAG_BADNN, first);
       continue;
     }
-    __syncthreads();
 
-    // ---- gather: scaled coordinates, y, X (lanes = local rows)
+    // ---- gather: scaled coordinates (zero-padded to DMAX), y, X
     if (lane < kk) {
-      const int64_t s = idx[lane];
-      const double* zs = a.locs + s * d;
-      for (int k = 0; k < d; ++k) Z[lane * SZ + k] = zs[k] * invrho[k];
-      V[lane] = a.y[s];
-      for (int t = 0; t < p; ++t) V[(1 + t) * SV + lane] = a.X[s * p + t];
+      const double* zs = a.locs + src * d;
+      double z[DMAX];
+#pragma unroll
+      for (int k = 0; k < DMAX; ++k) z[k] = (k < d) ? zs[k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < DMAX; ++k) Z[lane * SZ + k] = z[k] * invrho[k];
+      V[lane] = a.y[src];
+      for (int t = 0; t < p; ++t) V[(1 + t) * SV + lane] = a.X[src * p + t];
     }
-    __syncthreads();
+    wave_fence();
 
-    // ---- covariance (lower) and range-derivative pair factor (upper)
+    // ---- covariance (transposed, upper) and pair factors (lower)
     const int npair = kk * (kk + 1) / 2;
     for (int e = lane; e < npair; e += kLanes) {
       const int t = tri[e];
-      const int r = t & 0xffff, c = t >> 16;
+      const int r = t & 0xffff, cc = t >> 16;
       const double* zr = Z + r * SZ;
-      const double* zc = Z + c * SZ;
+      const double* zc = Z + cc * SZ;
       double h2 = 0.0;
-      for (int k = 0; k < d; ++k) {
+#pragma unroll
+      for (int k = 0; k < DMAX; ++k) {
         const double dz = zr[k] - zc[k];
         h2 = fma(dz, dz, h2);
       }
@@ -166,92 +226,139 @@ __global__ __launch_bounds__(kLanes) void aniso_kernel(const AnisoArgs a) {
         f = (1.0 + h + h * h / 3.0) * E;
         F = (1.0 + h) * E / 3.0;
       }
-      A[r * SA + c] = sigma2 * (f + (r == c ? tau2 : 0.0));
-      if (r != c) A[c * SA + r] = sigma2 * F;
+      A[cc * SA + r] = sigma2 * (f + (r == cc ? tau2 : 0.0));
+      if (r != cc) A[r * SA + cc] = sigma2 * F;
     }
-    __syncthreads();
+    wave_fence();
 
-    // ---- Cholesky, lower triangle in place; dinv[c] = 1 / L_cc
+    // ---- Cholesky in registers: lane r holds row r; the entries of column
+    // cc are broadcast lane by lane (readlane into scalar registers).  Rows
+    // and columns >= kk carry garbage that never reaches a row < kk
+    // (right-looking updates only flow to larger indices).
     bool notpd = false;
-    for (int c = 0; c < kk; ++c) {
-      const double piv = A[c * SA + c];
-      if (!(piv > 0.0)) {  // the same value in every lane
-        notpd = true;
-        break;
+    {
+      double Ar[KMAX];
+#pragma unroll
+      for (int cc = 0; cc < KMAX; ++cc) Ar[cc] = A[cc * SA + (lane < KMAX ? lane : 0)];
+#pragma unroll
+      for (int cc = 0; cc < KMAX; ++cc) {
+        const double piv = readlane_d(Ar[cc], cc);
+        if (cc < kk) notpd = notpd || !(piv > 0.0);
+        const double inv = rsqrt_nr(piv);
+        const double lrc = Ar[cc] * inv;
+        Ar[cc] = lrc;
+        if (lane == 0) dinv[cc] = inv;
+#pragma unroll
+        for (int s = cc + 1; s < KMAX; ++s) Ar[s] = fma(-lrc, readlane_d(lrc, s), Ar[s]);
       }
-      const double inv = 1.0 / sqrt(piv);
-      if (lane == 0) dinv[c] = inv;
-      for (int r = c + 1 + lane; r < kk; r += kLanes) A[r * SA + c] *= inv;
-      __syncthreads();
-      const int nt = kk - 1 - c, ntri = nt * (nt + 1) / 2;
-      for (int e = lane; e < ntri; e += kLanes) {
-        const int t = tri[e];
-        const int r = c + 1 + (t & 0xffff), s = c + 1 + (t >> 16);
-        A[r * SA + s] = fma(-A[r * SA + c], A[s * SA + c], A[r * SA + s]);
+      // L transposed into the upper triangle: A[cc][r] = L_r,cc for cc <= r
+      if (lane < kk) {
+#pragma unroll
+        for (int cc = 0; cc < KMAX; ++cc)
+          if (cc <= lane) A[cc * SA + lane] = Ar[cc];
       }
-      __syncthreads();
     }
     if (notpd) {
-      if (lane == 0) {
-        atomicOr(&a.status[0], VEC_FLAG_NOTPD);
-        atomicMin(&a.status[1], (int32_t)i);
-      }
-      __syncthreads();
+      if (lane == 0) flag(a.status, VEC_FLAG_NOTPD, first);
       continue;
     }
+    wave_fence();
 
-    // ---- u = L^-T e_q by back substitution (lane r holds u_r)
-    double ub = (lane == q) ? 1.0 : 0.0;
-    for (int c = q; c >= 0; --c) {
-      const double uc = readlane_d(ub, c) * dinv[c];
-      if (lane < c)
-        ub = fma(-A[c * SA + lane], uc, ub);
-      else if (lane == c)
-        ub = uc;
-    }
-    double* __restrict__ U = V + (NR - 1) * SV;
-    if (lane < kk) U[lane] = ub;
-    __syncthreads();
+    // solved columns of this block: y, X, then g per range, then g for U
+    const int NR = 1 + p + (R + 1) * g;
+    const int oU = 1 + p + R * g;
 
-    // ---- g_k[r] = sum_b F_rb s_k(r, b)^2 u_b / rho_k
+    // ---- U = L^-T E_B by back substitution (lane r holds U[r][t])
     {
-      constexpr int H = kLanes / KMAX;  // column halves
-      const int r = lane % KMAX, half = lane / KMAX;
+      double ub[GMAX];
+#pragma unroll
+      for (int t = 0; t < GMAX; ++t) ub[t] = (lane == c + t) ? 1.0 : 0.0;
+      for (int col = kk - 1; col >= 0; --col) {
+        const double dc = dinv[col];
+        const double lcl = (lane < col) ? A[lane * SA + col] : 0.0;  // L[col][lane]
+#pragma unroll
+        for (int t = 0; t < GMAX; ++t) {
+          if (t < g) {
+            const double uc = readlane_d(ub[t], col) * dc;
+            if (lane < col)
+              ub[t] = fma(-lcl, uc, ub[t]);
+            else if (lane == col)
+              ub[t] = uc;
+          }
+        }
+      }
+      if (lane < kk) {
+#pragma unroll
+        for (int t = 0; t < GMAX; ++t)
+          if (t < g) V[(oU + t) * SV + lane] = ub[t];
+      }
+    }
+    wave_fence();
+
+    // ---- G_j[r][t] = sum_b F_rb s_j(r, b)^2 U[b][t] / rho_j
+    {
+      constexpr int H = kLanes / KMAX > 1 ? 2 : 1;  // column halves
+      const int r = lane % KMAX, half = (H == 2) ? lane / (kLanes / 2) : 0;
+      const bool rowl = (H == 2) ? (lane % (kLanes / 2)) == r : true;
       const int hb = (kk + H - 1) / H;
       const int b0 = half * hb, b1 = (b0 + hb < kk) ? b0 + hb : kk;
-      double zr[DMAX], g[DMAX];
+      double zr[DMAX], gs[DMAX][GMAX];
 #pragma unroll
       for (int k = 0; k < DMAX; ++k) {
-        zr[k] = (k < d && r < kk) ? Z[r * SZ + k] : 0.0;
-        g[k] = 0.0;
+        zr[k] = Z[r * SZ + k];
+#pragma unroll
+        for (int t = 0; t < GMAX; ++t) gs[k][t] = 0.0;
       }
-      if (r < kk) {
+      if (r < kk && rowl) {
         for (int b = b0; b < b1; ++b) {
           if (b == r) continue;
           const int lo = b < r ? b : r, hi = b < r ? r : b;
-          const double cb = A[lo * SA + hi] * U[b];
+          const double F = A[hi * SA + lo];
+          double cb[GMAX];
+#pragma unroll
+          for (int t = 0; t < GMAX; ++t) cb[t] = (t < g) ? F * V[(oU + t) * SV + b] : 0.0;
           const double* zb = Z + b * SZ;
 #pragma unroll
           for (int k = 0; k < DMAX; ++k) {
-            if (k < d) {
-              const double s = zr[k] - zb[k];
-              g[k] = fma(cb * s, s, g[k]);
-            }
+            const double s = zr[k] - zb[k];
+            const double s2 = s * s;
+#pragma unroll
+            for (int t = 0; t < GMAX; ++t) gs[k][t] = fma(cb[t], s2, gs[k][t]);
           }
         }
       }
       if constexpr (H == 2) {
 #pragma unroll
         for (int k = 0; k < DMAX; ++k)
-          if (k < d) g[k] += __shfl_xor(g[k], 32);
-      }
-      if (half == 0 && r < kk) {
 #pragma unroll
-        for (int k = 0; k < DMAX; ++k)
-          if (k < d) V[(1 + p + k) * SV + r] = g[k] * invrho[k];
+          for (int t = 0; t < GMAX; ++t) gs[k][t] += __shfl_xor(gs[k][t], kLanes / 2);
+      }
+      if (half == 0 && r < kk && rowl) {
+#pragma unroll
+        for (int t = 0; t < GMAX; ++t) {
+          if (t >= g) continue;
+          if (per_coord) {
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k)
+              if (k < d) V[(1 + p + k * g + t) * SV + r] = gs[k][t] * invrho[k];
+          } else {  // coordinates sharing a range add up
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) {
+              if (k < d) {
+                if (grp(k) == 0)
+                  s0 += gs[k][t] * invrho[k];
+                else
+                  s1 += gs[k][t] * invrho[k];
+              }
+            }
+            V[(1 + p + t) * SV + r] = s0;
+            if (R > 1) V[(1 + p + g + t) * SV + r] = s1;
+          }
+        }
       }
     }
-    __syncthreads();
+    wave_fence();
 
     // ---- L^-1 applied to every column (one column per lane)
     if (lane < NR) {
@@ -266,102 +373,135 @@ __global__ __launch_bounds__(kLanes) void aniso_kernel(const AnisoArgs a) {
           for (int r = rb; r < rb + 8; ++r) {
             double s = vj[r];
 #pragma unroll
-            for (int c = 0; c < r; ++c) s = fma(-A[r * SA + c], x[c], s);
+            for (int cc = 0; cc < r; ++cc) s = fma(-A[cc * SA + r], x[cc], s);
             x[r] = s * dinv[r];
             if (r < kk) vj[r] = x[r];
           }
         }
       }
     }
-    __syncthreads();
+    wave_fence();
 
-    // ---- Gram matrix of the solved columns over the rows l < q
+    // ---- Gram matrix of the solved columns over the conditioning rows
     const int ng = NR * (NR + 1) / 2;
     for (int e = lane; e < ng; e += kLanes) {
       const int t = tri[e];
       const int j = t & 0xffff, k = t >> 16;
       const double* vj = V + j * SV;
       const double* vk = V + k * SV;
-      double s = 0.0;
-      for (int l = 0; l < q; ++l) s = fma(vj[l], vk[l], s);
-      G[j * NR + k] = s;
-      G[k * NR + j] = s;
-    }
-    __syncthreads();
-
-    // ---- the self row's terms, entry by entry (lane-owned accumulators)
-    const double Lyq = V[q];
-    bool finite = isfinite(Lyq);
-    for (int t = 0; t < p; ++t) finite = finite && isfinite(V[(1 + t) * SV + q]);
-    if (!finite) {
-      if (lane == 0) {
-        atomicOr(&a.status[0], VEC_FLAG_NONFINITE);
-        atomicMin(&a.status[1], (int32_t)i);
+      double s0 = 0.0, s1 = 0.0;
+      int l = 0;
+      for (; l + 1 < c; l += 2) {
+        s0 = fma(vj[l], vk[l], s0);
+        s1 = fma(vj[l + 1], vk[l + 1], s1);
       }
-      __syncthreads();
+      if (l < c) s0 = fma(vj[l], vk[l], s0);
+      G[j * NR + k] = s0 + s1;
+      G[k * NR + j] = s0 + s1;
+    }
+    wave_fence();
+
+    // ---- the block rows' terms, entry by entry (lane-owned accumulators)
+    bool finite = true;
+    for (int t = 0; t < g; ++t) {
+      finite = finite && isfinite(V[c + t]);
+      for (int s = 0; s < p; ++s) finite = finite && isfinite(V[(1 + s) * SV + c + t]);
+    }
+    if (!finite) {
+      if (lane == 0) flag(a.status, VEC_FLAG_NONFINITE, first);
       continue;
     }
-    // parameter j: 0 = sigma2, 1..d = rho_j, P - 1 = tau2
-    auto col = [&](int j) { return j == P - 1 ? NR - 1 : p + j; };
-    auto cf = [&](int j) { return j == 0 ? 0.0 : (j == P - 1 ? sigma2 : 1.0); };
-    auto wq = [&](int j) { return j == 0 ? 1.0 / sigma2 : cf(j) * V[col(j) * SV + q]; };
-    auto Sy = [&](int j) { return j == 0 ? 0.0 : cf(j) * G[col(j) * NR]; };
-    auto SX = [&](int j, int t) { return j == 0 ? 0.0 : cf(j) * G[col(j) * NR + 1 + t]; };
-    auto Gjk = [&](int j, int k) {
-      return (j == 0 || k == 0) ? 0.0 : cf(j) * cf(k) * G[col(j) * NR + col(k)];
+    // parameter j: 0 = sigma2, 1..R = ranges, P - 1 = tau2; column of
+    // parameter j >= 1 for block row t
+    auto col = [&](int j, int t) { return j == P - 1 ? oU + t : 1 + p + (j - 1) * g + t; };
+    auto cf = [&](int j) { return j == P - 1 ? sigma2 : 1.0; };
+    auto zB = [&](int t) { return V[c + t]; };
+    auto XB = [&](int t, int s) { return V[(1 + s) * SV + c + t]; };
+    // W_j[c + rr][t]
+    auto wq = [&](int j, int rr, int t) {
+      return j == 0 ? (rr == t ? 1.0 / sigma2 : 0.0) : cf(j) * V[col(j, t) * SV + c + rr];
     };
-    auto LX = [&](int t) { return V[(1 + t) * SV + q]; };
+    auto Sy = [&](int j, int t) { return j == 0 ? 0.0 : cf(j) * G[col(j, t) * NR]; };
+    auto SX = [&](int j, int t, int s) {
+      return j == 0 ? 0.0 : cf(j) * G[col(j, t) * NR + 1 + s];
+    };
+    auto GG = [&](int j, int k, int t) {
+      return (j == 0 || k == 0) ? 0.0 : cf(j) * cf(k) * G[col(j, t) * NR + col(k, t)];
+    };
     for (int e = lane; e < nraw; e += kLanes) {
       int o = e;
-      double v;
+      double v = 0.0;
       if (o == 0) {
-        v = -2.0 * log(dinv[q]);
+        for (int t = 0; t < g; ++t) v += -2.0 * log(dinv[c + t]);
       } else if (o == 1) {
-        v = Lyq * Lyq;
+        for (int t = 0; t < g; ++t) v += zB(t) * zB(t);
       } else if ((o -= 2) < p * p) {
-        v = LX(o / p) * LX(o % p);
+        for (int t = 0; t < g; ++t) v += XB(t, o / p) * XB(t, o % p);
       } else if ((o -= p * p) < p) {
-        v = Lyq * LX(o);
+        for (int t = 0; t < g; ++t) v += zB(t) * XB(t, o);
       } else if ((o -= p) < P) {
-        v = wq(o);
+        for (int t = 0; t < g; ++t) v += wq(o, t, t);
       } else if ((o -= P) < P) {
-        v = -2.0 * Lyq * Sy(o) - wq(o) * Lyq * Lyq;
+        const int j = o;
+        for (int t = 0; t < g; ++t) {
+          v += -2.0 * zB(t) * Sy(j, t);
+          for (int rr = 0; rr < g; ++rr) v -= zB(rr) * wq(j, rr, t) * zB(t);
+        }
       } else if ((o -= P) < P * p * p) {
-        const int j = o / (p * p), st = o % (p * p), s = st / p, t = st % p;
-        v = -(SX(j, s) * LX(t) + LX(s) * SX(j, t)) - wq(j) * LX(s) * LX(t);
+        const int j = o / (p * p), st = o % (p * p), s = st / p, s2 = st % p;
+        for (int t = 0; t < g; ++t) {
+          v -= XB(t, s) * SX(j, t, s2) + SX(j, t, s) * XB(t, s2);
+          for (int rr = 0; rr < g; ++rr) v -= XB(rr, s) * wq(j, rr, t) * XB(t, s2);
+        }
       } else if ((o -= P * p * p) < P * p) {
-        const int j = o / p, t = o % p;
-        v = -Sy(j) * LX(t) - Lyq * SX(j, t) - wq(j) * Lyq * LX(t);
+        const int j = o / p, s = o % p;
+        for (int t = 0; t < g; ++t) {
+          v -= zB(t) * SX(j, t, s) + Sy(j, t) * XB(t, s);
+          for (int rr = 0; rr < g; ++rr) v -= zB(rr) * wq(j, rr, t) * XB(t, s);
+        }
       } else {
         o -= P * p;
         const int j = o / P, k = o % P;
-        v = Gjk(j, k) + 0.5 * wq(j) * wq(k);
+        for (int t = 0; t < g; ++t) {
+          v += GG(j, k, t);
+          for (int rr = 0; rr < g; ++rr) v += 0.5 * wq(j, rr, t) * wq(k, rr, t);
+        }
       }
       acc[e] += v;
     }
-    __syncthreads();
+    wave_fence();
   }
   double* out = a.partials + (int64_t)blockIdx.x * nraw;
   for (int e = lane; e < nraw; e += kLanes) out[e] = acc[e];
 }
 
-template <int KMAX, int DMAX>
-hipError_t launch_t(const AnisoArgs& a, int grid, hipStream_t st) {
-  const Layout L = layout_of(KMAX, a.d, a.p);
+template <int KMAX, int DMAX, int GMAX>
+hipError_t launch_t(const WaveArgs& a, int grid, hipStream_t st) {
+  const Layout L = layout_of(KMAX, DMAX, a.R, a.p, a.block_start ? a.gmax : 1);
   const size_t bytes = (size_t)L.total * sizeof(double);
   if (bytes > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(aniso_kernel<KMAX, DMAX>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)bytes);
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(wave_kernel<KMAX, DMAX, GMAX>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((aniso_kernel<KMAX, DMAX>), dim3(grid), dim3(kLanes), bytes, st, a);
+  hipLaunchKernelGGL((wave_kernel<KMAX, DMAX, GMAX>), dim3(grid), dim3(kLanes), bytes, st, a);
   return hipGetLastError();
+}
+
+template <int KMAX>
+hipError_t launch_k(const WaveArgs& a, int grid, hipStream_t st) {
+  if (a.block_start && a.gmax > 1) return launch_t<KMAX, 4, kMaxBlock>(a, grid, st);
+  if (a.d <= 4) return launch_t<KMAX, 4, 1>(a, grid, st);
+  if (a.d <= 8) return launch_t<KMAX, 8, 1>(a, grid, st);
+  if (a.d <= 16) return launch_t<KMAX, 16, 1>(a, grid, st);
+  if (a.d <= 20) return launch_t<KMAX, 20, 1>(a, grid, st);
+  return launch_t<KMAX, 32, 1>(a, grid, st);
 }
 
 }  // namespace
 
-int aniso_grid(int64_t total) {
+int wave_grid(int64_t total) {
   if (total <= 0) return 0;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -373,12 +513,12 @@ int aniso_grid(int64_t total) {
   return (int)(total < cap ? total : cap);
 }
 
-hipError_t launch_aniso(const AnisoArgs& a, int grid, hipStream_t st) {
+hipError_t launch_wave(const WaveArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  const bool small = a.m + 1 <= 32;
-  if (a.d <= 8) return small ? launch_t<32, 8>(a, grid, st) : launch_t<64, 8>(a, grid, st);
-  if (a.d <= 16) return small ? launch_t<32, 16>(a, grid, st) : launch_t<64, 16>(a, grid, st);
-  return small ? launch_t<32, 32>(a, grid, st) : launch_t<64, 32>(a, grid, st);
+  const int kmax = a.block_start ? a.m + a.gmax : a.m + 1;
+  if (kmax <= 16) return launch_k<16>(a, grid, st);
+  if (kmax <= 32) return launch_k<32>(a, grid, st);
+  return launch_k<64>(a, grid, st);
 }
 
-}  // namespace vecchia_aniso
+}  // namespace vecchia_wave

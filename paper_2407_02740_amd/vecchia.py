@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvecchia.so")
@@ -94,6 +95,17 @@ def lib():
         L.vec_maxmin_order.restype = ctypes.c_int
         L.vec_maxmin_order.argtypes = [ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
                                        ctypes.c_size_t, _VP]
+        L.vec_grouped_workspace_bytes.restype = ctypes.c_size_t
+        L.vec_grouped_workspace_bytes.argtypes = [pp, ctypes.c_int64]
+        L.vec_grouped_raw_sums.restype = ctypes.c_int
+        L.vec_grouped_raw_sums.argtypes = [pp, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP,
+                                           ctypes.c_int64, ctypes.c_int32, _VP, _VP,
+                                           ctypes.c_size_t, _VP, _VP]
+        L.vec_grouped_fisher_fit.restype = ctypes.c_int
+        L.vec_grouped_fisher_fit.argtypes = [pp, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP,
+                                             ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_double, _VP, _VP, _VP, ctypes.c_size_t, _VP,
+                                             ctypes.c_int32, _VP]
         L.vec_fisher_update.restype = ctypes.c_int
         L.vec_fisher_update.argtypes = [pp, _VP, _VP, _VP, ctypes.c_double, _VP]
         L.vec_fisher_fit.restype = ctypes.c_int
@@ -372,6 +384,79 @@ def maxmin_order(locs, tie, device: str = "cuda"):
                                   out.data_ptr(), ws.data_ptr(), nb, _stream()),
            "vec_maxmin_order")
     return order, out
+
+
+class GroupedVecchia(Vecchia):
+    """Grouped Vecchia (vec_grouped_*): consecutive blocks of observations
+    [block_start[b], block_start[b + 1]) with conditioning sets
+    cond[cond_start[b]:cond_start[b + 1]] of earlier observations."""
+
+    def __init__(self, locs, y, X, block_start, cond_start, cond, family: int = FAMILY_ISO,
+                 smoothness: float = 0.5, nspace: int = 0, device: str = "cuda"):
+        bs = np.asarray(block_start, dtype=np.int64)
+        cs = np.asarray(cond_start, dtype=np.int64)
+        m = int(np.diff(cs).max()) if len(cs) > 1 else 0
+        self.max_block = int(np.diff(bs).max()) if len(bs) > 1 else 1
+        self.nblocks = len(bs) - 1
+        n = len(np.asarray(y))
+        dummy_nn = np.zeros((1, m + 1), dtype=np.int32)
+        super().__init__(locs, dummy_nn, y, X, family, smoothness, nspace, device)
+        self.pb.n = n
+        self.n = n
+        self.block_start = torch.as_tensor(bs, device=self.device)
+        self.cond_start = torch.as_tensor(cs, device=self.device)
+        c = np.asarray(cond, dtype=np.int32)
+        self.cond = torch.as_tensor(c if c.size else np.zeros(1, np.int32), device=self.device)
+        self.ncond = int(c.size)
+
+    def workspace(self, i0: int = 0, i1: int | None = None) -> torch.Tensor:
+        nb = lib().vec_grouped_workspace_bytes(ctypes.byref(self.pb), self.nblocks)
+        if nb == 0:
+            raise VecchiaError(VEC_EINVAL, "vec_grouped_workspace_bytes")
+        if self._ws is None or self._ws.numel() * 8 < nb:
+            self._ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        return self._ws
+
+    def _blocks(self):
+        return (self.nblocks, self.block_start.data_ptr(), self.cond_start.data_ptr(),
+                self.cond.data_ptr(), self.ncond, self.max_block)
+
+    def raw_sums(self, covparms, i0: int = 0, i1: int | None = None, check: bool = True):
+        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
+            self.covparms(covparms)
+        ws = self.workspace()
+        _check(lib().vec_grouped_raw_sums(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.y.data_ptr(), self.X.data_ptr(),
+            _dev(cp, torch.float64, "covparms"), *self._blocks(), self.raw.data_ptr(),
+            ws.data_ptr(), ws.numel() * 8, self.status.data_ptr(), _stream()),
+            "vec_grouped_raw_sums")
+        if check:
+            self.check_status("vec_grouped_raw_sums")
+        return self.raw
+
+    def loglik_grad_info(self, covparms, check: bool = True):
+        self.raw_sums(covparms, check=False)
+        _check(lib().vec_combine(ctypes.byref(self.pb), self.raw.data_ptr(), self.out.data_ptr(),
+                                 self.status.data_ptr(), _stream()), "vec_combine")
+        if check:
+            self.check_status("grouped loglik_grad_info")
+        return self.out
+
+    def fisher_fit(self, covparms: torch.Tensor, iters: int, use_graph: bool = True,
+                   max_step: float = 1.0, check: bool = True):
+        ws = self.workspace()
+        _check(lib().vec_grouped_fisher_fit(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.y.data_ptr(), self.X.data_ptr(),
+            _dev(covparms, torch.float64, "covparms"), *self._blocks(), int(iters),
+            float(max_step), self.raw.data_ptr(), self.out.data_ptr(), ws.data_ptr(),
+            ws.numel() * 8, self.status.data_ptr(), int(bool(use_graph)), _stream()),
+            "vec_grouped_fisher_fit")
+        if check:
+            self.check_status("vec_grouped_fisher_fit")
+        return covparms
+
+    def block_sums(self, *args, **kwargs):
+        raise NotImplementedError("grouped problems reduce on the device (raw_sums)")
 
 
 class Predictor:

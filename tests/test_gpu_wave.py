@@ -1,9 +1,11 @@
-"""Parity of the one-range-per-coordinate family (the wave-per-neighbourhood
-kernel) with the CPU oracle, through the C ABI, at the tolerances of
-test_gpu_parity: the full 18-attribute workload element by element, and a
-sweep of dimensions, neighbour counts, covariates and smoothness values that
-spans both kernel sizes (m + 1 <= 32 and <= 64) and every coordinate block
-(d <= 8, 16, 32), with ragged first neighbourhoods (i < m)."""
+"""Parity of the wave-per-neighbourhood kernel with the CPU oracle, through
+the C ABI, at the tolerances of test_gpu_parity: the one-range-per-coordinate
+family on the full 18-attribute workload element by element and over a sweep
+of dimensions, neighbour counts, covariates and smoothness values that spans
+every kernel size (m + 1 <= 16, 32, 64) and coordinate block (d <= 4, 8, 16,
+20, 32), with ragged first neighbourhoods (i < m); and the isotropic and
+space-time families beyond the fused kernel's largest neighbourhood
+(40 < m <= 63)."""
 
 import numpy as np
 import pytest
@@ -70,6 +72,27 @@ def test_attributes_18d_full_size():
 def test_shapes_match_the_oracle(d, m, p, nu):
     n = 1500 if m > 31 else 2500
     run_case(_problem(n, d, m, p, nu, seed=100 * d + m), f"d{d}m{m}p{p}")
+
+
+@pytest.mark.parametrize("family,nu,m,p", [(0, 0.5, 60, 1), (0, 1.5, 45, 2), (1, 0.5, 60, 1),
+                                           (1, 2.5, 63, 3)])
+def test_isotropic_and_space_time_beyond_the_fused_sizes(family, nu, m, p):
+    rng = np.random.default_rng(m + 10 * family)
+    n = 3000
+    d = 2 if family == 0 else 3
+    locs = rng.random((n, d))
+    locs = locs[S.maxmin_exact(locs)]
+    cp = np.array((1.3, 0.15, 0.05)) if family == 0 else np.array((1.1, 0.3, 0.5, 0.1))
+    scaled = locs / (cp[1] if family == 0 else np.array([cp[1], cp[1], cp[2]]))
+    NN = S.find_ordered_nn(scaled, m)
+    y = rng.standard_normal(n)
+    X = np.column_stack([np.ones(n)] + [rng.standard_normal(n) for _ in range(p - 1)])
+    _say(f"case family={family} nu={nu} m={m} p={p}")
+    ev = V.Vecchia(locs, NN, y, X, family, nu, 2 if family == 1 else 0)
+    got = V.unpack_out(ev.loglik_grad_info(cp), p, ev.P)
+    ref_raw = oracle.raw_sums(locs, NN, y, X, cp, family, nu, nspace=2, threads=8)
+    check_raw(ev.raw.cpu().numpy(), ref_raw, p, ev.P, f"m{m}")
+    check_outputs(got, oracle.combine(ref_raw, n, p, ev.P), f"m{m}")
 
 
 def test_tiny_inputs_and_ranges_of_observations():
