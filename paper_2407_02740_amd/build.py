@@ -41,7 +41,8 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     # largest translation units first so the pool finishes early
-    srcs.sort(key=lambda s: ("_k41" not in s, "_k31" not in s, "_k21" not in s, s))
+    srcs.sort(key=lambda s: ("vecchia_wave" not in s, "_k41" not in s, "_k31" not in s,
+                             "_k21" not in s, s))
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -242,14 +242,16 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
       for (int cc = 0; cc < KMAX; ++cc) Ar[cc] = A[cc * SA + (lane < KMAX ? lane : 0)];
 #pragma unroll
       for (int cc = 0; cc < KMAX; ++cc) {
-        const double piv = readlane_d(Ar[cc], cc);
-        if (cc < kk) notpd = notpd || !(piv > 0.0);
-        const double inv = rsqrt_nr(piv);
-        const double lrc = Ar[cc] * inv;
-        Ar[cc] = lrc;
-        if (lane == 0) dinv[cc] = inv;
+        if (cc < kk) {  // columns past the neighbourhood are skipped whole
+          const double piv = readlane_d(Ar[cc], cc);
+          notpd = notpd || !(piv > 0.0);
+          const double inv = rsqrt_nr(piv);
+          const double lrc = Ar[cc] * inv;
+          Ar[cc] = lrc;
+          if (lane == 0) dinv[cc] = inv;
 #pragma unroll
-        for (int s = cc + 1; s < KMAX; ++s) Ar[s] = fma(-lrc, readlane_d(lrc, s), Ar[s]);
+          for (int s = cc + 1; s < KMAX; ++s) Ar[s] = fma(-lrc, readlane_d(lrc, s), Ar[s]);
+        }
       }
       // L transposed into the upper triangle: A[cc][r] = L_r,cc for cc <= r
       if (lane < kk) {
@@ -491,7 +493,9 @@ hipError_t launch_t(const WaveArgs& a, int grid, hipStream_t st) {
 
 template <int KMAX>
 hipError_t launch_k(const WaveArgs& a, int grid, hipStream_t st) {
-  if (a.block_start && a.gmax > 1) return launch_t<KMAX, 4, kMaxBlock>(a, grid, st);
+  if (a.block_start && a.gmax > 4) return launch_t<KMAX, 4, 8>(a, grid, st);
+  if (a.block_start && a.gmax > 2) return launch_t<KMAX, 4, 4>(a, grid, st);
+  if (a.block_start && a.gmax > 1) return launch_t<KMAX, 4, 2>(a, grid, st);
   if (a.d <= 4) return launch_t<KMAX, 4, 1>(a, grid, st);
   if (a.d <= 8) return launch_t<KMAX, 8, 1>(a, grid, st);
   if (a.d <= 16) return launch_t<KMAX, 16, 1>(a, grid, st);
@@ -518,6 +522,7 @@ hipError_t launch_wave(const WaveArgs& a, int grid, hipStream_t st) {
   const int kmax = a.block_start ? a.m + a.gmax : a.m + 1;
   if (kmax <= 16) return launch_k<16>(a, grid, st);
   if (kmax <= 32) return launch_k<32>(a, grid, st);
+  if (kmax <= 48) return launch_k<48>(a, grid, st);
   return launch_k<64>(a, grid, st);
 }
 
