@@ -17,6 +17,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <rocprim/device/device_scan.hpp>
+
 #include "point_box.hpp"
 #include "vecchia.h"
 
@@ -58,32 +60,12 @@ __global__ void cell_kernel(int64_t b1, const double* __restrict__ locs, const G
   atomicAdd(&count[c], 1);
 }
 
-// start[c] = sum of count[0..c) (one workgroup, fixed order); start[ncells]
-// = total; cursor[c] = start[c]
-__global__ __launch_bounds__(1024) void scan_kernel(int64_t ncells, const int32_t* __restrict__ count,
-                                                    int32_t* __restrict__ start,
-                                                    int32_t* __restrict__ cursor) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (ncells + 1023) / 1024;
-  const int64_t a = t * per, b = (a + per < ncells) ? a + per : ncells;
-  int32_t s = 0;
-  for (int64_t c = a; c < b; ++c) s += count[c];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
-    const int32_t v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int32_t run = (t > 0) ? part[t - 1] : 0;
-  for (int64_t c = a; c < b; ++c) {
-    start[c] = run;
-    cursor[c] = run;
-    run += count[c];
-  }
-  if (t == 1023) start[ncells] = part[1023];
+// cursor[c] = start[c] for the scatter
+__global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
 }
 
 template <int D>
@@ -209,10 +191,22 @@ int64_t max_cells(int64_t n) { return n / kPerCell + 8 * 8 * 8 + 1; }
 
 struct Work {
   double* box;
+  double* box_partial;
+  void* scan_tmp;
+  size_t scan_bytes;
   int32_t *cell, *count, *start, *cursor, *sidx;
   double* sxyz;
   size_t bytes;
 };
+
+// the library's temporary bytes of an exclusive scan of `count` int32 values
+size_t scan_bytes_for(int64_t count) {
+  size_t b = 0;
+  if (rocprim::exclusive_scan(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr, 0,
+                              (size_t)count, rocprim::plus<int32_t>()) != hipSuccess)
+    return 0;
+  return b;
+}
 
 Work carve(void* ws, int64_t n, int d) {
   Work w = {};
@@ -225,6 +219,9 @@ Work carve(void* ws, int64_t n, int d) {
   };
   const int64_t nc = max_cells(n);
   w.box = reinterpret_cast<double*>(take(2 * kMaxD * sizeof(double)));
+  w.box_partial = reinterpret_cast<double*>(take(vecchia_box::bbox_partial_bytes(kMaxD)));
+  w.scan_bytes = scan_bytes_for(nc + 1);
+  w.scan_tmp = take(w.scan_bytes);
   w.cell = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
   w.count = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
   w.start = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
@@ -285,7 +282,7 @@ Grid make_grid(const double* lo, const double* hi, int d, int64_t b1) {
 
 template <int D>
 int run(int64_t n, int m, const double* locs, int32_t* NN, const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(vecchia_box::bbox_kernel<D>, dim3(1), dim3(256), 0, st, n, locs, w.box);
+  vecchia_box::enqueue_bbox<D>(n, locs, w.box_partial, w.box, st);
   double box[2 * kMaxD];
   if (hipMemcpyAsync(box, w.box, 2 * D * sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
@@ -299,8 +296,13 @@ int run(int64_t n, int m, const double* locs, int32_t* NN, const Work& w, hipStr
     const unsigned nb = (unsigned)((b1 + 255) / 256);
     hipLaunchKernelGGL(zero_i32_kernel, dim3(256), dim3(256), 0, st, w.count, g.ncells + 1);
     hipLaunchKernelGGL(cell_kernel<D>, dim3(nb), dim3(256), 0, st, b1, locs, g, w.cell, w.count);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, g.ncells, w.count, w.start,
-                       w.cursor);
+    // start[c] = sum of count[0..c), start[ncells] = the total; cursor = start
+    size_t sb = w.scan_bytes;
+    if (rocprim::exclusive_scan(w.scan_tmp, sb, (const int32_t*)w.count, w.start, 0,
+                                (size_t)(g.ncells + 1), rocprim::plus<int32_t>(), st) != hipSuccess)
+      return VEC_EHIP;
+    hipLaunchKernelGGL(copy_i32_kernel, dim3(256), dim3(256), 0, st, w.start, w.cursor,
+                       g.ncells + 1);
     hipLaunchKernelGGL(scatter_kernel<D>, dim3(nb), dim3(256), 0, st, b1, locs, w.cell, w.cursor,
                        w.sidx, w.sxyz);
     const unsigned nq = (unsigned)((b1 - b0 + kQueryThreads - 1) / kQueryThreads);

@@ -119,6 +119,7 @@ int grid_bits(int64_t n, int d) {
 
 struct Work {
   double* box;
+  double* box_partial;
   uint64_t *rev, *k0, *k1;
   int32_t *v0, *v1;
   void* sort_tmp;
@@ -152,6 +153,7 @@ Work carve(void* ws, int64_t n, size_t sort_bytes, size_t scan_bytes) {
     return q;
   };
   w.box = reinterpret_cast<double*>(take(2 * kMaxD * sizeof(double)));
+  w.box_partial = reinterpret_cast<double*>(take(vecchia_box::bbox_partial_bytes(kMaxD)));
   w.rev = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
   w.k0 = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
   w.k1 = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
@@ -170,7 +172,7 @@ int run(int64_t n, const double* locs, const double* tie, int64_t* order, double
         Work& w, hipStream_t st) {
   const int B = grid_bits(n, D);
   const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(vecchia_box::bbox_kernel<D>, dim3(1), dim3(256), 0, st, n, locs, w.box);
+  vecchia_box::enqueue_bbox<D>(n, locs, w.box_partial, w.box, st);
   hipLaunchKernelGGL(key_kernel<D>, dim3(nb), dim3(kThreads), 0, st, n, B, locs, w.box, tie, w.rev,
                      w.k0, w.v0);
   rocprim::double_buffer<uint64_t> keys(w.k0, w.k1);

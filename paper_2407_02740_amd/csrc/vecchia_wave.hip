@@ -107,6 +107,24 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(y0 * e, fma(0.375, e, 0.5), y0);
 }
 
+// Profiling builds only (-DVECCHIA_WAVE_TIMING, with a device array
+// unsigned long long wave_cycles[16] defined before this file is compiled):
+// shader-clock cycles of each step of the block loop, summed over waves.
+#ifdef VECCHIA_WAVE_TIMING
+#define WAVE_TDECL unsigned long long t_last_ = clock64();
+#define WAVE_TMARK(idx)                                      \
+  do {                                                       \
+    __builtin_amdgcn_sched_barrier(0);                       \
+    const unsigned long long t_ = clock64();                 \
+    if (lane == 0) atomicAdd(&wave_cycles[idx], t_ - t_last_); \
+    t_last_ = t_;                                            \
+    __builtin_amdgcn_sched_barrier(0);                       \
+  } while (0)
+#else
+#define WAVE_TDECL
+#define WAVE_TMARK(idx)
+#endif
+
 __device__ __forceinline__ void flag(int32_t* status, int f, int64_t i) {
   atomicOr(&status[0], f);
   atomicMin(&status[1], (int32_t)i);
@@ -146,6 +164,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
   for (int k = lane; k < kMaxD; k += kLanes) invrho[k] = (k < d) ? 1.0 / a.covparms[1 + grp(k)] : 0.0;
   for (int e = lane; e < nraw; e += kLanes) acc[e] = 0.0;
   wave_fence();
+  WAVE_TDECL
 
   for (int64_t u = a.i0 + blockIdx.x; u < a.i1; u += gridDim.x) {
     // ---- the block: first member, size g, conditioning set (c entries)
@@ -187,6 +206,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
       continue;
     }
 
+    WAVE_TMARK(0);
     // ---- gather: scaled coordinates (zero-padded to DMAX), y, X
     if (lane < kk) {
       const double* zs = a.locs + src * d;
@@ -200,6 +220,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     }
     wave_fence();
 
+    WAVE_TMARK(1);
     // ---- covariance (transposed, upper) and pair factors (lower)
     const int npair = kk * (kk + 1) / 2;
     for (int e = lane; e < npair; e += kLanes) {
@@ -231,6 +252,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     }
     wave_fence();
 
+    WAVE_TMARK(2);
     // ---- Cholesky in registers: lane r holds row r; the entries of column
     // cc are broadcast lane by lane (readlane into scalar registers).  Rows
     // and columns >= kk carry garbage that never reaches a row < kk
@@ -270,6 +292,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     const int NR = 1 + p + (R + 1) * g;
     const int oU = 1 + p + R * g;
 
+    WAVE_TMARK(3);
     // ---- U = L^-T E_B by back substitution (lane r holds U[r][t])
     {
       double ub[GMAX];
@@ -297,6 +320,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     }
     wave_fence();
 
+    WAVE_TMARK(4);
     // ---- G_j[r][t] = sum_b F_rb s_j(r, b)^2 U[b][t] / rho_j
     {
       constexpr int H = kLanes / KMAX > 1 ? 2 : 1;  // column halves
@@ -362,6 +386,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     }
     wave_fence();
 
+    WAVE_TMARK(5);
     // ---- L^-1 applied to every column (one column per lane)
     if (lane < NR) {
       double* __restrict__ vj = V + lane * SV;
@@ -384,6 +409,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     }
     wave_fence();
 
+    WAVE_TMARK(6);
     // ---- Gram matrix of the solved columns over the conditioning rows
     const int ng = NR * (NR + 1) / 2;
     for (int e = lane; e < ng; e += kLanes) {
@@ -403,6 +429,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     }
     wave_fence();
 
+    WAVE_TMARK(7);
     // ---- the block rows' terms, entry by entry (lane-owned accumulators)
     bool finite = true;
     for (int t = 0; t < g; ++t) {
@@ -472,6 +499,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
       acc[e] += v;
     }
     wave_fence();
+    WAVE_TMARK(8);
   }
   double* out = a.partials + (int64_t)blockIdx.x * nraw;
   for (int e = lane; e < nraw; e += kLanes) out[e] = acc[e];
