@@ -462,10 +462,14 @@ def bench_surrogate(args):
 
 
 def bench_sweep(args):
-    """Throughput over problem sizes and neighbour counts (2-D Matern 3/2,
-    loglik + gradient + Fisher): kernel-only time (HIP events, median of the
-    repetitions) and end-to-end time from host arrays (host-to-device copies,
-    evaluation, result back on the host)."""
+    """Throughput over problem sizes and neighbour counts, the grid of the
+    paper's size study (n = 2^15 .. 2^22, m = 10, 30, 60; plus m = 40): 2-D
+    Matern 3/2 (1.0, 0.05, 0.05), loglik + gradient + Fisher; kernel-only
+    time (HIP events, median of the repetitions) and end-to-end time from host
+    arrays (host-to-device copies, evaluation, result back on the host).
+    Points uniform on the unit square in the coarse-to-fine order, the
+    neighbour arrays from the library's own search (m = 60, columns cut for
+    smaller m), y a random-Fourier-feature draw plus nugget."""
     import statistics
 
     import numpy as np
@@ -477,14 +481,19 @@ def bench_sweep(args):
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     rows = []
-    for n in (1 << 15, 1 << 17, 1 << 19):
-        base = S.surrogate_plane(seed=7, n=n, m=40, log=None)
-        for m in (10, 30, 40):
-            NN = np.ascontiguousarray(base["NN"][:, :m + 1])
-            cp = np.array(base["covparms"])
+    cp = np.array((1.0, 0.05, 0.05))
+    for n in (1 << 15, 1 << 17, 1 << 19, 1 << 21, 1 << 22):
+        rng = np.random.default_rng(7)
+        locs = rng.random((n, 2))
+        locs = np.ascontiguousarray(locs[S.maxmin_approx(locs, 7)])
+        NN60 = V.ordered_nn(torch.as_tensor(locs, device="cuda"), 60).cpu().numpy()
+        y = S.rff_field(locs / cp[1], 1.5, 128, rng) + np.sqrt(cp[2]) * rng.standard_normal(n)
+        X = np.ones((n, 1))
+        for m in (10, 30, 40, 60):
+            NN = np.ascontiguousarray(NN60[:, :m + 1])
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
-                ev = V.Vecchia(base["locs"], NN, base["y"], base["X"], V.FAMILY_ISO, 1.5, 0)
+                ev = V.Vecchia(locs, NN, y, X, V.FAMILY_ISO, 1.5, 0)
                 cpd = ev.covparms(cp)
                 ev.loglik_grad_info(cpd, check=False)
                 times = []
@@ -498,14 +507,17 @@ def bench_sweep(args):
                     times.append(e0.elapsed_time(e1))
             ev.check_status("sweep")
             kern = statistics.median(times)
+            del ev
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             with torch.cuda.stream(stream):
-                ev2 = V.Vecchia(base["locs"], NN, base["y"], base["X"], V.FAMILY_ISO, 1.5, 0)
+                ev2 = V.Vecchia(locs, NN, y, X, V.FAMILY_ISO, 1.5, 0)
                 out = ev2.loglik_grad_info(ev2.covparms(cp), check=False).cpu()
             e2e = (time.perf_counter() - t0) * 1e3
+            del ev2
             row = dict(n=n, m=m, kernel_ms=kern, nbhd_per_s=n / (kern * 1e-3), end_to_end_ms=e2e,
-                       end_to_end_nbhd_per_s=n / (e2e * 1e-3), loglik=float(out[0]))
+                       end_to_end_nbhd_per_s=n / (e2e * 1e-3), loglik=float(out[0]),
+                       kernel="fused" if m + 1 <= 41 else "wave")
             rows.append(row)
             log(f"n={n} m={m}: {kern:.3f} ms ({row['nbhd_per_s']:.3e} nbhd/s), end to end "
                 f"{e2e:.1f} ms")

@@ -52,7 +52,7 @@ constexpr int kLanes = 64;
 // Offsets (in doubles) of the per-workgroup LDS regions.
 struct Layout {
   int SA, SZ, SV, NR, P, nraw;
-  int oA, oZ, oV, oG, oAcc, oDinv, oInvRho, oTri, total;
+  int oA, oZ, oV, oG, oAcc, oDinv, oInvRho, oTri, oDesc, total;
 };
 
 // kmax: neighbourhood rows; dmax: coordinate slots per row (the slots
@@ -84,6 +84,8 @@ __host__ __device__ inline Layout layout_of(int kmax, int dmax, int R, int p, in
   o += kMaxD;
   L.oTri = o;
   o += (T * (T + 1) / 2 + 1) / 2;
+  L.oDesc = o;  // one int32 per raw entry
+  o += (L.nraw + 1) / 2;
   L.total = o;
   return L;
 }
@@ -111,18 +113,24 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // unsigned long long wave_cycles[16] defined before this file is compiled):
 // shader-clock cycles of each step of the block loop, summed over waves.
 #ifdef VECCHIA_WAVE_TIMING
-#define WAVE_TDECL unsigned long long t_last_ = clock64();
-#define WAVE_TMARK(idx)                                      \
-  do {                                                       \
-    __builtin_amdgcn_sched_barrier(0);                       \
-    const unsigned long long t_ = clock64();                 \
-    if (lane == 0) atomicAdd(&wave_cycles[idx], t_ - t_last_); \
-    t_last_ = t_;                                            \
-    __builtin_amdgcn_sched_barrier(0);                       \
+#define WAVE_TDECL                     \
+  unsigned long long tsec_[9] = {};    \
+  unsigned long long t_last_ = clock64();
+#define WAVE_TMARK(idx)                          \
+  do {                                           \
+    __builtin_amdgcn_sched_barrier(0);           \
+    const unsigned long long t_ = clock64();     \
+    tsec_[idx] += t_ - t_last_;                  \
+    t_last_ = t_;                                \
+    __builtin_amdgcn_sched_barrier(0);           \
   } while (0)
+#define WAVE_TFLUSH \
+  if (lane == 0)    \
+    for (int k_ = 0; k_ < 9; ++k_) atomicAdd(&wave_cycles[k_], tsec_[k_]);
 #else
 #define WAVE_TDECL
 #define WAVE_TMARK(idx)
+#define WAVE_TFLUSH
 #endif
 
 __device__ __forceinline__ void flag(int32_t* status, int f, int64_t i) {
@@ -150,6 +158,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
   double* __restrict__ dinv = lds + Ly.oDinv;
   double* __restrict__ invrho = lds + Ly.oInvRho;
   int32_t* __restrict__ tri = reinterpret_cast<int32_t*>(lds + Ly.oTri);
+  int32_t* __restrict__ edesc = reinterpret_cast<int32_t*>(lds + Ly.oDesc);
 
   const double sigma2 = a.covparms[0], tau2 = a.covparms[R + 1];
   // range parameter of coordinate k
@@ -162,7 +171,34 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
   for (int r = lane; r < T; r += kLanes)
     for (int c = 0; c <= r; ++c) tri[r * (r + 1) / 2 + c] = r | (c << 16);
   for (int k = lane; k < kMaxD; k += kLanes) invrho[k] = (k < d) ? 1.0 / a.covparms[1 + grp(k)] : 0.0;
-  for (int e = lane; e < nraw; e += kLanes) acc[e] = 0.0;
+  // edesc[e]: what raw entry e is -- kind (0 logdet, 1 ySy, 2 XSX, 3 ySX,
+  // 4 dlogdet, 5 dySy, 6 dXSX, 7 dySX, 8 ainfo) | j << 4 | k << 10 |
+  // s << 16 | s2 << 18 (parameters j, k; covariates s, s2)
+  for (int e = lane; e < nraw; e += kLanes) {
+    acc[e] = 0.0;
+    int o = e, kind, j = 0, k = 0, s1 = 0, s2 = 0;
+    if (o == 0) {
+      kind = 0;
+    } else if (o == 1) {
+      kind = 1;
+    } else if ((o -= 2) < p * p) {
+      kind = 2, s1 = o / p, s2 = o % p;
+    } else if ((o -= p * p) < p) {
+      kind = 3, s1 = o;
+    } else if ((o -= p) < P) {
+      kind = 4, j = o;
+    } else if ((o -= P) < P) {
+      kind = 5, j = o;
+    } else if ((o -= P) < P * p * p) {
+      kind = 6, j = o / (p * p), s1 = (o % (p * p)) / p, s2 = o % p;
+    } else if ((o -= P * p * p) < P * p) {
+      kind = 7, j = o / p, s1 = o % p;
+    } else {
+      o -= P * p;
+      kind = 8, j = o / P, k = o % P;
+    }
+    edesc[e] = kind | (j << 4) | (k << 10) | (s1 << 16) | (s2 << 18);
+  }
   wave_fence();
   WAVE_TDECL
 
@@ -336,14 +372,32 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
         for (int t = 0; t < GMAX; ++t) gs[k][t] = 0.0;
       }
       if (r < kk && rowl) {
+        // with many coordinates the next column's are loaded while this
+        // one's are used
+        constexpr bool kAhead = DMAX >= 8;
+        double zn[DMAX];
+        if constexpr (kAhead) {
+#pragma unroll
+          for (int k = 0; k < DMAX; ++k) zn[k] = Z[b0 * SZ + k];
+        }
         for (int b = b0; b < b1; ++b) {
+          double zb[DMAX];
+          if constexpr (kAhead) {
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) zb[k] = zn[k];
+            const int bn = (b + 1 < b1) ? b + 1 : b;
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) zn[k] = Z[bn * SZ + k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) zb[k] = Z[b * SZ + k];
+          }
           if (b == r) continue;
           const int lo = b < r ? b : r, hi = b < r ? r : b;
           const double F = A[hi * SA + lo];
           double cb[GMAX];
 #pragma unroll
           for (int t = 0; t < GMAX; ++t) cb[t] = (t < g) ? F * V[(oU + t) * SV + b] : 0.0;
-          const double* zb = Z + b * SZ;
 #pragma unroll
           for (int k = 0; k < DMAX; ++k) {
             const double s = zr[k] - zb[k];
@@ -458,49 +512,57 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
       return (j == 0 || k == 0) ? 0.0 : cf(j) * cf(k) * G[col(j, t) * NR + col(k, t)];
     };
     for (int e = lane; e < nraw; e += kLanes) {
-      int o = e;
+      const int code = edesc[e];
+      const int kind = code & 15, j = (code >> 4) & 63, k = (code >> 10) & 63,
+                s = (code >> 16) & 3, s2 = (code >> 18) & 3;
       double v = 0.0;
-      if (o == 0) {
-        for (int t = 0; t < g; ++t) v += -2.0 * log(dinv[c + t]);
-      } else if (o == 1) {
-        for (int t = 0; t < g; ++t) v += zB(t) * zB(t);
-      } else if ((o -= 2) < p * p) {
-        for (int t = 0; t < g; ++t) v += XB(t, o / p) * XB(t, o % p);
-      } else if ((o -= p * p) < p) {
-        for (int t = 0; t < g; ++t) v += zB(t) * XB(t, o);
-      } else if ((o -= p) < P) {
-        for (int t = 0; t < g; ++t) v += wq(o, t, t);
-      } else if ((o -= P) < P) {
-        const int j = o;
-        for (int t = 0; t < g; ++t) {
-          v += -2.0 * zB(t) * Sy(j, t);
-          for (int rr = 0; rr < g; ++rr) v -= zB(rr) * wq(j, rr, t) * zB(t);
-        }
-      } else if ((o -= P) < P * p * p) {
-        const int j = o / (p * p), st = o % (p * p), s = st / p, s2 = st % p;
-        for (int t = 0; t < g; ++t) {
-          v -= XB(t, s) * SX(j, t, s2) + SX(j, t, s) * XB(t, s2);
-          for (int rr = 0; rr < g; ++rr) v -= XB(rr, s) * wq(j, rr, t) * XB(t, s2);
-        }
-      } else if ((o -= P * p * p) < P * p) {
-        const int j = o / p, s = o % p;
-        for (int t = 0; t < g; ++t) {
-          v -= zB(t) * SX(j, t, s) + Sy(j, t) * XB(t, s);
-          for (int rr = 0; rr < g; ++rr) v -= zB(rr) * wq(j, rr, t) * XB(t, s);
-        }
-      } else {
-        o -= P * p;
-        const int j = o / P, k = o % P;
-        for (int t = 0; t < g; ++t) {
-          v += GG(j, k, t);
-          for (int rr = 0; rr < g; ++rr) v += 0.5 * wq(j, rr, t) * wq(k, rr, t);
-        }
+      switch (kind) {
+        case 0:
+          for (int t = 0; t < g; ++t) v += -2.0 * log(dinv[c + t]);
+          break;
+        case 1:
+          for (int t = 0; t < g; ++t) v += zB(t) * zB(t);
+          break;
+        case 2:
+          for (int t = 0; t < g; ++t) v += XB(t, s) * XB(t, s2);
+          break;
+        case 3:
+          for (int t = 0; t < g; ++t) v += zB(t) * XB(t, s);
+          break;
+        case 4:
+          for (int t = 0; t < g; ++t) v += wq(j, t, t);
+          break;
+        case 5:
+          for (int t = 0; t < g; ++t) {
+            v += -2.0 * zB(t) * Sy(j, t);
+            for (int rr = 0; rr < g; ++rr) v -= zB(rr) * wq(j, rr, t) * zB(t);
+          }
+          break;
+        case 6:
+          for (int t = 0; t < g; ++t) {
+            v -= XB(t, s) * SX(j, t, s2) + SX(j, t, s) * XB(t, s2);
+            for (int rr = 0; rr < g; ++rr) v -= XB(rr, s) * wq(j, rr, t) * XB(t, s2);
+          }
+          break;
+        case 7:
+          for (int t = 0; t < g; ++t) {
+            v -= zB(t) * SX(j, t, s) + Sy(j, t) * XB(t, s);
+            for (int rr = 0; rr < g; ++rr) v -= zB(rr) * wq(j, rr, t) * XB(t, s);
+          }
+          break;
+        default:
+          for (int t = 0; t < g; ++t) {
+            v += GG(j, k, t);
+            for (int rr = 0; rr < g; ++rr) v += 0.5 * wq(j, rr, t) * wq(k, rr, t);
+          }
+          break;
       }
       acc[e] += v;
     }
     wave_fence();
     WAVE_TMARK(8);
   }
+  WAVE_TFLUSH
   double* out = a.partials + (int64_t)blockIdx.x * nraw;
   for (int e = lane; e < nraw; e += kLanes) out[e] = acc[e];
 }
