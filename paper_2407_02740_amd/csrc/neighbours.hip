@@ -13,6 +13,11 @@
 // cell sides, so the search stops once the m-th best distance is below that.
 // Candidates within a cell may be visited in any order; the (distance,
 // index) order makes the result unique.
+//
+// With more than three coordinates a grid no longer prunes well; there the
+// search is exhaustive (O(n^2) distances): each workgroup of 64 queries
+// walks the earlier points in tiles staged through LDS (every lane reads the
+// same candidate, a broadcast), keeping the same sorted candidate lists.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -24,7 +29,8 @@
 
 namespace vecchia_nn {
 
-constexpr int kMaxD = 3;
+constexpr int kMaxD = 3;        // grid search
+constexpr int kMaxDBrute = 32;  // exhaustive search
 constexpr int kQueryThreads = 64;
 constexpr int kPerCell = 3;
 constexpr int kMaxM = 64;
@@ -169,6 +175,63 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
   int32_t* row = NN + i * (int64_t)(m + 1);
   row[0] = (int32_t)i;
   for (int q = 0; q < m; ++q) row[1 + q] = (q < cnt) ? bj(q) : -1;
+#undef bd
+#undef bj
+}
+
+// Exhaustive ordered search for d > 3: queries [0, n) in workgroups of 64,
+// candidates j < i in tiles of 64 points (LDS: tile[64][d], then the
+// per-lane lists as in query_kernel).
+__global__ __launch_bounds__(kQueryThreads) void brute_kernel(int64_t n, int d, int m,
+                                                              const double* __restrict__ locs,
+                                                              int32_t* __restrict__ NN) {
+  extern __shared__ double dyn[];
+  double* __restrict__ tile = dyn;                              // [kQueryThreads][d]
+  double* __restrict__ xq = dyn + (size_t)kQueryThreads * d;       // [kQueryThreads][d]
+  double* __restrict__ bdv = dyn + (size_t)2 * kQueryThreads * d;  // [m][kQueryThreads]
+  int32_t* __restrict__ bjv = reinterpret_cast<int32_t*>(bdv + (size_t)(m > 0 ? m : 1) * kQueryThreads);
+  const int t = threadIdx.x;
+#define bd(q) bdv[(q) * kQueryThreads + t]
+#define bj(q) bjv[(q) * kQueryThreads + t]
+  const int64_t i0 = blockIdx.x * (int64_t)kQueryThreads;
+  const int64_t i = i0 + t;
+  const bool live = i < n;
+  const int me = live ? (int)(i < m ? i : m) : 0;
+  for (int k = 0; k < d; ++k) xq[t * d + k] = live ? locs[i * d + k] : 0.0;
+  int cnt = 0;
+  const int64_t jend = (i0 + kQueryThreads < n) ? i0 + kQueryThreads : n;  // candidates < jend
+  for (int64_t j0 = 0; j0 < jend; j0 += kQueryThreads) {
+    const int64_t tn = (jend - j0 < kQueryThreads) ? jend - j0 : kQueryThreads;
+    __syncthreads();
+    for (int64_t e = t; e < tn * d; e += kQueryThreads) tile[e] = locs[j0 * d + e];
+    __syncthreads();
+    if (me > 0) {
+      for (int jj = 0; jj < (int)tn; ++jj) {
+        const int64_t j = j0 + jj;
+        if (j >= i) break;
+        double d2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double dz = tile[jj * d + k] - xq[t * d + k];
+          d2 = fma(dz, dz, d2);
+        }
+        if (cnt == me && !before(d2, (int32_t)j, bd(me - 1), bj(me - 1))) continue;
+        int q = (cnt < me) ? cnt : me - 1;
+        while (q > 0 && before(d2, (int32_t)j, bd(q - 1), bj(q - 1))) {
+          bd(q) = bd(q - 1);
+          bj(q) = bj(q - 1);
+          --q;
+        }
+        bd(q) = d2;
+        bj(q) = (int32_t)j;
+        if (cnt < me) ++cnt;
+      }
+    }
+  }
+  if (live) {
+    int32_t* row = NN + i * (int64_t)(m + 1);
+    row[0] = (int32_t)i;
+    for (int q = 0; q < m; ++q) row[1 + q] = (q < cnt) ? bj(q) : -1;
+  }
 #undef bd
 #undef bj
 }
@@ -321,19 +384,35 @@ int run(int64_t n, int m, const double* locs, int32_t* NN, const Work& w, hipStr
 extern "C" {
 
 size_t vec_ordered_nn_workspace_bytes(int64_t n, int32_t d, int32_t m) {
-  if (n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxD || m < 0 || m > kMaxM) return 0;
+  if (n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxDBrute || m < 0 || m > kMaxM) return 0;
+  if (d > kMaxD) return 256;  // the exhaustive search needs none; a token size
   return carve(nullptr, n, d).bytes;
 }
 
 int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t* NNarray,
                    void* workspace, size_t workspace_bytes, void* stream) {
-  if (n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxD || m < 0 || m > kMaxM || !locs ||
-      !NNarray)
+  if (n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxDBrute || m < 0 || m > kMaxM ||
+      !locs || !NNarray)
     return VEC_EINVAL;
   const size_t need = vec_ordered_nn_workspace_bytes(n, d, m);
   if (!workspace || workspace_bytes < need) return VEC_EWORKSPACE;
-  const Work w = carve(workspace, n, d);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (d > kMaxD) {
+    const unsigned nb = (unsigned)((n + kQueryThreads - 1) / kQueryThreads);
+    const size_t lds = ((size_t)2 * kQueryThreads * d + (size_t)(m > 0 ? m : 1) * kQueryThreads) *
+                           sizeof(double) +
+                       (size_t)(m > 0 ? m : 1) * kQueryThreads * sizeof(int32_t);
+    if (lds > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(brute_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+      if (e != hipSuccess) return VEC_EHIP;
+    }
+    hipLaunchKernelGGL(brute_kernel, dim3(nb), dim3(kQueryThreads), lds, st, n, (int)d, (int)m,
+                       locs, NNarray);
+    return hipGetLastError() == hipSuccess ? VEC_OK : VEC_EHIP;
+  }
+  const Work w = carve(workspace, n, d);
   if (d == 1) return run<1>(n, m, locs, NNarray, w, st);
   if (d == 2) return run<2>(n, m, locs, NNarray, w, st);
   return run<3>(n, m, locs, NNarray, w, st);

@@ -63,3 +63,19 @@ def test_space_time_scaled_3d():
     scaled = w["locs"][:, :3] / 0.0872388
     got = V.ordered_nn(scaled, 30).cpu().numpy()
     np.testing.assert_array_equal(got, S.find_ordered_nn(scaled, 30))
+
+
+@pytest.mark.parametrize("d,m", [(4, 0), (4, 10), (7, 1), (18, 30), (32, 64), (9, 40)])
+def test_exhaustive_search_in_more_dimensions(d, m):
+    rng = np.random.default_rng(100 + d + m)
+    locs = rng.standard_normal((1200, d)) * np.linspace(0.5, 2.0, d)
+    got = V.ordered_nn(locs, m).cpu().numpy()
+    np.testing.assert_array_equal(got, brute(locs, m))
+
+
+def test_attribute_workload_neighbours():
+    # the 18-attribute workload: neighbours in range-scaled coordinates
+    w = S.attributes_18d()
+    rho = w["covparms"][1:-1]
+    got = V.ordered_nn(w["locs"] / rho, w["m"]).cpu().numpy()
+    np.testing.assert_array_equal(got, w["NN"])
