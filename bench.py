@@ -709,6 +709,20 @@ def bench_attributes(args):
         cpu = {"value": n / dtc, "unit": "neighbourhoods/s", "cores": threads, "kind": "oracle",
                "sample": f"all {n} neighbourhoods of the workload, {dtc:.2f} s wall"}
     res = V.unpack_out(ev.out, p, ev.P)
+    # the neighbour arrays of this workload on the device (exhaustive search
+    # in 18 range-scaled coordinates) against the host k-d tree search
+    scaled = torch.as_tensor(w["locs"] / w["covparms"][1:-1], device="cuda")
+    V.ordered_nn(scaled, m)
+    torch.cuda.synchronize()
+    tn = time.perf_counter()
+    NNd = V.ordered_nn(scaled, m)
+    torch.cuda.synchronize()
+    nn_ms = 1e3 * (time.perf_counter() - tn)
+    th = time.perf_counter()
+    NNh = S.find_ordered_nn(w["locs"] / w["covparms"][1:-1], m, workers=min(16, os.cpu_count() or 1))
+    nn_host_ms = 1e3 * (time.perf_counter() - th)
+    assert np.array_equal(NNd.cpu().numpy(), NNh), "device and host neighbour arrays differ"
+    log(f"neighbours: device {nn_ms:.2f} ms, host {nn_host_ms:.1f} ms")
     line = {
         "metric": "neighbourhoods/s (loglik+grad+Fisher), 18 attributes with one range each, "
                   "n=14939 m=30",
@@ -727,7 +741,8 @@ def bench_attributes(args):
         "cpu_baseline": cpu,
         "detail": {"kernel": f"wave_kernel<{32 if m + 1 <= 32 else 64}, 20, 1>", "kernel_ms": kernel_ms,
                    "flop_per_neighbourhood": F, "fit_40_iterations_ms": 1e3 * fit40,
-                   "loglik": res["loglik"]},
+                   "loglik": res["loglik"], "neighbours_device_ms": nn_ms,
+                   "neighbours_host_ms": nn_host_ms},
     }
     print(json.dumps(line), flush=True)
 
