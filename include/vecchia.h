@@ -225,16 +225,16 @@ int vec_kriging_predict(const vec_problem* pb, const double* locs, const int32_t
  * it in Euclidean distance, written as NNarray[i] = [i, nearest first, ...,
  * -1 padding] (n rows of m + 1 int32; ties in distance go to the smaller
  * index, so the result is unique).  Scale the coordinates beforehand for
- * anisotropic ranges.  m <= 64.  d <= 3: a grid search (the call reads the
+ * anisotropic ranges.  m <= 64.  d <= 4: a grid search (the call reads the
  * bounding box back to the host, so it synchronises `stream` once);
- * 3 < d <= 32: an exhaustive search, O(n^2) distances (meant for the
+ * 4 < d <= 32: an exhaustive search, O(n^2) distances (meant for the
  * higher-dimensional problems of Section 4.2, tens of thousands of points).
  * workspace: vec_ordered_nn_workspace_bytes(n, d, m) bytes. */
 size_t vec_ordered_nn_workspace_bytes(int64_t n, int32_t d, int32_t m);
 int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t* NNarray,
                    void* workspace, size_t workspace_bytes, void* stream);
 
-/* Coarse-to-fine ordering of locs[n][d] (d = 1, 2 or 3), an approximation of
+/* Coarse-to-fine ordering of locs[n][d] (1 <= d <= 4), an approximation of
  * the maxmin ordering that Section 2.1 builds the conditioning sets on.
  * Coordinates are quantised to a 2^B grid over the bounding box,
  * B = min(max(1, ceil(log2(max(n, 2)) / d)), floor(60 / d)); the cell code

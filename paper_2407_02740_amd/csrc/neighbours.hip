@@ -14,7 +14,7 @@
 // Candidates within a cell may be visited in any order; the (distance,
 // index) order makes the result unique.
 //
-// With more than three coordinates a grid no longer prunes well; there the
+// With more than four coordinates a grid no longer prunes well; there the
 // search is exhaustive (O(n^2) distances): each workgroup of 64 queries
 // walks the earlier points in tiles staged through LDS (every lane reads the
 // same candidate, a broadcast), keeping the same sorted candidate lists.
@@ -29,7 +29,7 @@
 
 namespace vecchia_nn {
 
-constexpr int kMaxD = 3;        // grid search
+constexpr int kMaxD = 4;        // grid search
 constexpr int kMaxDBrute = 32;  // exhaustive search
 constexpr int kQueryThreads = 64;
 constexpr int kPerCell = 3;
@@ -415,7 +415,8 @@ int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t*
   const Work w = carve(workspace, n, d);
   if (d == 1) return run<1>(n, m, locs, NNarray, w, st);
   if (d == 2) return run<2>(n, m, locs, NNarray, w, st);
-  return run<3>(n, m, locs, NNarray, w, st);
+  if (d == 3) return run<3>(n, m, locs, NNarray, w, st);
+  return run<4>(n, m, locs, NNarray, w, st);
 }
 
 }  // extern "C"

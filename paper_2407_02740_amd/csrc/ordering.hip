@@ -26,7 +26,7 @@
 
 namespace vecchia_order {
 
-constexpr int kMaxD = 3;
+constexpr int kMaxD = 4;
 constexpr int kThreads = 256;
 
 // order-preserving map of a finite double to an unsigned key
@@ -230,7 +230,8 @@ int vec_maxmin_order(int64_t n, int32_t d, const double* locs, const double* tie
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (d == 1) return run<1>(n, locs, tie, order, locs_out, w, st);
   if (d == 2) return run<2>(n, locs, tie, order, locs_out, w, st);
-  return run<3>(n, locs, tie, order, locs_out, w, st);
+  if (d == 3) return run<3>(n, locs, tie, order, locs_out, w, st);
+  return run<4>(n, locs, tie, order, locs_out, w, st);
 }
 
 }  // extern "C"

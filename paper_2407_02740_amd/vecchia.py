@@ -348,7 +348,8 @@ class Vecchia:
 
 def ordered_nn(locs, m: int, device: str = "cuda") -> torch.Tensor:
     """NNarray [n][m + 1] (int32, on the device) of the ordered points locs
-    ([n][d], d <= 3) by the library's neighbour search (vec_ordered_nn)."""
+    ([n][d], d <= 32; a grid search up to d = 4, exhaustive above) by the
+    library's neighbour search (vec_ordered_nn)."""
     x = torch.as_tensor(locs, dtype=torch.float64).to(device).contiguous()
     if x.dim() == 1:
         x = x[:, None].contiguous()
@@ -364,7 +365,7 @@ def ordered_nn(locs, m: int, device: str = "cuda") -> torch.Tensor:
 
 
 def maxmin_order(locs, tie, device: str = "cuda"):
-    """(order, reordered locs) of the points locs ([n][d], d <= 3) by the
+    """(order, reordered locs) of the points locs ([n][d], d <= 4) by the
     library's coarse-to-fine ordering (vec_maxmin_order); tie [n] breaks the
     order within a grid cell.  order is int64 on the device."""
     x = torch.as_tensor(locs, dtype=torch.float64).to(device).contiguous()

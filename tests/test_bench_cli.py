@@ -23,5 +23,5 @@ def test_workloads_are_listed():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 0
     for name in ("satellite_spacetime", "batched_uneven", "surrogate_plane", "sweep", "predict",
-                 "neighbours", "attributes_18d", "grouped_plane"):
+                 "neighbours", "attributes_18d", "grouped_plane", "pipeline"):
         assert name in p.stdout

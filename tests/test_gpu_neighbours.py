@@ -27,11 +27,11 @@ def brute(locs, m):
     return NN
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
 @pytest.mark.parametrize("m", [0, 1, 5, 30, 40])
 def test_brute_force_small(d, m):
     rng = np.random.default_rng(10 * d + m)
-    locs = rng.random((1500, d)) * np.array([1.0, 3.0, 0.5][:d])
+    locs = rng.random((1500, d)) * np.array([1.0, 3.0, 0.5, 2.0][:d])
     locs = locs[S.maxmin_exact(locs)]
     got = V.ordered_nn(locs, m).cpu().numpy()
     np.testing.assert_array_equal(got, brute(locs, m))
@@ -79,3 +79,16 @@ def test_attribute_workload_neighbours():
     rho = w["covparms"][1:-1]
     got = V.ordered_nn(w["locs"] / rho, w["m"]).cpu().numpy()
     np.testing.assert_array_equal(got, w["NN"])
+
+
+def test_space_time_scaled_4d_matches_the_host_search():
+    # the space-time workload's neighbour search: unit-sphere xyz / rho_s and
+    # time / rho_t, in the coarse-to-fine order
+    rng = np.random.default_rng(17)
+    lon, lat, t = S.satellite_tracks(16, 64, 256, rng)
+    la, lo = np.radians(lat), np.radians(lon)
+    xyz = np.column_stack([np.cos(la) * np.cos(lo), np.cos(la) * np.sin(lo), np.sin(la)])
+    scaled = np.column_stack([xyz / S.RHO_SPACE_5DEG, t / 3.0])
+    scaled = np.ascontiguousarray(scaled[S.maxmin_approx(scaled, 17)])
+    got = V.ordered_nn(scaled, 30).cpu().numpy()
+    np.testing.assert_array_equal(got, S.find_ordered_nn(scaled, 30))

@@ -24,11 +24,11 @@ def check(locs, tie):
     np.testing.assert_array_equal(out.cpu().numpy().reshape(locs.shape), locs[ref])
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
 @pytest.mark.parametrize("n", [1, 2, 3, 1000, 65_537, 1 << 20])
 def test_matches_the_host_ordering(d, n):
     rng = np.random.default_rng(100 * d + n % 97)
-    locs = rng.random((n, d)) * np.array([2.0, 1.0, 0.25][:d])
+    locs = rng.random((n, d)) * np.array([2.0, 1.0, 0.25, 3.0][:d])
     check(locs, rng.random(n))
 
 
