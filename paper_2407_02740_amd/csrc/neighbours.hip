@@ -4,7 +4,7 @@
 // factorisation), written as NNarray rows [i, nearest, ..., -1 padding].
 //
 // Observations are taken in doubling blocks [b0, b1) (the first block is
-// [0, head)).  For a block, a uniform grid with about kPerCell points per
+// [0, head)).  For a block, a uniform grid with about per_cell(d) points per
 // cell is built over observations [0, b1) (cell ids, counting sort by cell
 // with coordinates copied into cell order), and each observation i of the
 // block searches the grid in shells of growing Chebyshev radius around its
@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
 
 #include "point_box.hpp"
 #include "vecchia.h"
@@ -32,7 +33,12 @@ namespace vecchia_nn {
 constexpr int kMaxD = 4;        // grid search
 constexpr int kMaxDBrute = 32;  // exhaustive search
 constexpr int kQueryThreads = 64;
-constexpr int kPerCell = 3;
+#ifndef VECCHIA_NN_CELL4
+#define VECCHIA_NN_CELL4 3
+#endif
+// points per grid cell: small cells in one to three dimensions, larger in
+// four, where a shell of radius r holds (2r + 1)^4 cells
+__host__ __device__ constexpr int per_cell(int d) { return d >= 4 ? VECCHIA_NN_CELL4 : 3; }
 constexpr int kMaxM = 64;
 
 struct Grid {
@@ -92,9 +98,12 @@ __device__ __forceinline__ bool before(double d, int32_t j, double e, int32_t k)
 }
 
 template <int D>
+// Queries are taken in grid-cell order (qlist: the block's observations in
+// the order of the counting sort), so the lanes of a wave search the same
+// neighbourhood of cells.
 __global__ __launch_bounds__(kQueryThreads) void query_kernel(
-    int64_t b0, int64_t b1, int m, const double* __restrict__ locs, const Grid g,
-    const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
+    int64_t nq, const int32_t* __restrict__ qlist, int m, const double* __restrict__ locs,
+    const Grid g, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
     const double* __restrict__ sxyz, int32_t* __restrict__ NN) {
   // per thread: the m best distances and indices (dynamic LDS, m columns of
   // kQueryThreads entries each)
@@ -104,8 +113,9 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
   const int t = threadIdx.x;
 #define bd(q) bdv[(q) * kQueryThreads + t]
 #define bj(q) bjv[(q) * kQueryThreads + t]
-  const int64_t i = b0 + blockIdx.x * (int64_t)kQueryThreads + t;
-  if (i >= b1) return;
+  const int64_t qi = blockIdx.x * (int64_t)kQueryThreads + t;
+  if (qi >= nq) return;
+  const int64_t i = qlist[qi];
   const int me = (int)(i < m ? i : m);
   double xq[D];
   int h[D];
@@ -115,6 +125,8 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     h[k] = cell_coord(xq[k], g.lo[k], g.side, g.g[k]);
   }
   int cnt = 0;
+  double wd = 0.0;
+  int32_t wj = 0;
   int gmax = 1;
 #pragma unroll
   for (int k = 0; k < D; ++k) gmax = g.g[k] > gmax ? g.g[k] : gmax;
@@ -144,7 +156,7 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
             const double dz = sxyz[(int64_t)p * D + k] - xq[k];
             d2 = fma(dz, dz, d2);
           }
-          if (cnt == me && !before(d2, j, bd(me - 1), bj(me - 1))) continue;
+          if (cnt == me && !before(d2, j, wd, wj)) continue;
           // insert, keeping the list sorted
           int q = (cnt < me) ? cnt : me - 1;
           while (q > 0 && before(d2, j, bd(q - 1), bj(q - 1))) {
@@ -155,6 +167,10 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
           bd(q) = d2;
           bj(q) = j;
           if (cnt < me) ++cnt;
+          if (cnt == me) {  // the current m-th best, kept in registers
+            wd = bd(me - 1);
+            wj = bj(me - 1);
+          }
         }
       }
       // next offset of the cube [-r, r]^D
@@ -170,7 +186,7 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
       if (k == D) break;
     }
     const double reach = r * g.side;
-    if (cnt == me && bd(me - 1) < reach * reach) break;
+    if (cnt == me && wd < reach * reach) break;
   }
   int32_t* row = NN + i * (int64_t)(m + 1);
   row[0] = (int32_t)i;
@@ -250,13 +266,17 @@ int64_t head_of(int64_t n, int m) {
 }
 
 // the largest cell count any block's grid can have
-int64_t max_cells(int64_t n) { return n / kPerCell + 8 * 8 * 8 + 1; }
+int64_t max_cells(int64_t n, int d) { return n / per_cell(d) + 8 * 8 * 8 * 8 + 1; }
 
 struct Work {
   double* box;
   double* box_partial;
   void* scan_tmp;
   size_t scan_bytes;
+  void* sel_tmp;
+  size_t sel_bytes;
+  int32_t* qlist;
+  int64_t* qcount;
   int32_t *cell, *count, *start, *cursor, *sidx;
   double* sxyz;
   size_t bytes;
@@ -271,6 +291,20 @@ size_t scan_bytes_for(int64_t count) {
   return b;
 }
 
+struct AtLeast {
+  int32_t lo;
+  __device__ __host__ bool operator()(int32_t j) const { return j >= lo; }
+};
+
+// the library's temporary bytes of selecting from `count` int32 values
+size_t select_bytes_for(int64_t count) {
+  size_t b = 0;
+  if (rocprim::select(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr, (int64_t*)nullptr,
+                      (size_t)count, AtLeast{0}) != hipSuccess)
+    return 0;
+  return b;
+}
+
 Work carve(void* ws, int64_t n, int d) {
   Work w = {};
   char* p = static_cast<char*>(ws);
@@ -280,11 +314,15 @@ Work carve(void* ws, int64_t n, int d) {
     o += al256(b);
     return q;
   };
-  const int64_t nc = max_cells(n);
+  const int64_t nc = max_cells(n, d);
   w.box = reinterpret_cast<double*>(take(2 * kMaxD * sizeof(double)));
   w.box_partial = reinterpret_cast<double*>(take(vecchia_box::bbox_partial_bytes(kMaxD)));
   w.scan_bytes = scan_bytes_for(nc + 1);
   w.scan_tmp = take(w.scan_bytes);
+  w.sel_bytes = select_bytes_for(n);
+  w.sel_tmp = take(w.sel_bytes);
+  w.qlist = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+  w.qcount = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
   w.cell = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
   w.count = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
   w.start = reinterpret_cast<int32_t*>(take((nc + 1) * sizeof(int32_t)));
@@ -295,7 +333,7 @@ Work carve(void* ws, int64_t n, int d) {
   return w;
 }
 
-// grid over points [0, b1) inside the box: equal cell sides, about kPerCell
+// grid over points [0, b1) inside the box: equal cell sides, about per_cell(d)
 // points per cell (dimensions of negligible extent get one cell)
 Grid make_grid(const double* lo, const double* hi, int d, int64_t b1) {
   Grid g = {};
@@ -312,7 +350,7 @@ Grid make_grid(const double* lo, const double* hi, int d, int64_t b1) {
       ++dd;
     }
   }
-  const double target = (double)(b1 / kPerCell > 1 ? b1 / kPerCell : 1);
+  const double target = (double)(b1 / per_cell(d) > 1 ? b1 / per_cell(d) : 1);
   double side = (dd > 0 && vol > 0.0) ? pow(vol / target, 1.0 / dd) : 1.0;
   if (!(side > 0.0)) side = 1.0;
   int64_t nc = 1;
@@ -324,7 +362,7 @@ Grid make_grid(const double* lo, const double* hi, int d, int64_t b1) {
     nc *= gk;
   }
   // the rounding up can overshoot the target; widen until within bounds
-  while (nc > max_cells(b1) - 1) {
+  while (nc > max_cells(b1, d) - 1) {
     side *= 1.1;
     nc = 1;
     for (int k = 0; k < d; ++k) {
@@ -370,8 +408,13 @@ int run(int64_t n, int m, const double* locs, int32_t* NN, const Work& w, hipStr
                        w.sidx, w.sxyz);
     const unsigned nq = (unsigned)((b1 - b0 + kQueryThreads - 1) / kQueryThreads);
     const size_t lds = (size_t)(m > 0 ? m : 1) * kQueryThreads * (sizeof(double) + sizeof(int32_t));
-    hipLaunchKernelGGL(query_kernel<D>, dim3(nq), dim3(kQueryThreads), lds, st, b0, b1, m, locs, g,
-                       w.start, w.sidx, w.sxyz, NN);
+    // the block's observations (indices >= b0) in cell order
+    size_t sb2 = w.sel_bytes;
+    if (rocprim::select(w.sel_tmp, sb2, (const int32_t*)w.sidx, w.qlist, w.qcount, (size_t)b1,
+                        AtLeast{(int32_t)b0}, st) != hipSuccess)
+      return VEC_EHIP;
+    hipLaunchKernelGGL(query_kernel<D>, dim3(nq), dim3(kQueryThreads), lds, st, b1 - b0, w.qlist,
+                       m, locs, g, w.start, w.sidx, w.sxyz, NN);
     if (hipGetLastError() != hipSuccess) return VEC_EHIP;
     b0 = b1;
     b1 = 2 * b1 < n ? 2 * b1 : n;
