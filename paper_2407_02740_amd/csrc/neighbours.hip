@@ -15,9 +15,9 @@
 // index) order makes the result unique.
 //
 // With more than four coordinates a grid no longer prunes well; there the
-// search is exhaustive (O(n^2) distances): each workgroup of 64 queries
-// walks the earlier points in tiles staged through LDS (every lane reads the
-// same candidate, a broadcast), keeping the same sorted candidate lists.
+// search is exhaustive (O(n^2) distances): each workgroup of 16 queries (four
+// lanes each) walks the earlier points in tiles staged through LDS, keeping
+// the same sorted candidate lists, merged per query at the end.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -195,42 +195,54 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
 #undef bj
 }
 
-// Exhaustive ordered search for d > 3: queries [0, n) in workgroups of 64,
-// candidates j < i in tiles of 64 points (LDS: tile[64][d], then the
-// per-lane lists as in query_kernel).
+// Exhaustive ordered search for d > 4: 16 queries per workgroup of 64
+// lanes, four lanes per query splitting the candidates j < i (lane part p
+// takes j = p (mod 4) of every tile), candidates in tiles of 64 points
+// staged through LDS (tile[64][d]); each lane keeps a sorted list as in
+// query_kernel, and the first lane of a query merges the four lists.
+constexpr int kBruteQueries = 16;
+constexpr int kBruteSplit = kQueryThreads / kBruteQueries;
+
 __global__ __launch_bounds__(kQueryThreads) void brute_kernel(int64_t n, int d, int m,
                                                               const double* __restrict__ locs,
                                                               int32_t* __restrict__ NN) {
   extern __shared__ double dyn[];
-  double* __restrict__ tile = dyn;                              // [kQueryThreads][d]
-  double* __restrict__ xq = dyn + (size_t)kQueryThreads * d;       // [kQueryThreads][d]
-  double* __restrict__ bdv = dyn + (size_t)2 * kQueryThreads * d;  // [m][kQueryThreads]
+  double* __restrict__ tile = dyn;                                 // [kQueryThreads][d]
+  double* __restrict__ xq = dyn + (size_t)kQueryThreads * d;        // [kBruteQueries][d]
+  double* __restrict__ bdv = xq + (size_t)kBruteQueries * d;         // [m][kQueryThreads]
   int32_t* __restrict__ bjv = reinterpret_cast<int32_t*>(bdv + (size_t)(m > 0 ? m : 1) * kQueryThreads);
+  int32_t* __restrict__ cnts = bjv + (size_t)(m > 0 ? m : 1) * kQueryThreads;  // [kQueryThreads]
   const int t = threadIdx.x;
+  const int qloc = t / kBruteSplit, part = t % kBruteSplit;
 #define bd(q) bdv[(q) * kQueryThreads + t]
 #define bj(q) bjv[(q) * kQueryThreads + t]
-  const int64_t i0 = blockIdx.x * (int64_t)kQueryThreads;
-  const int64_t i = i0 + t;
+  const int64_t i0 = blockIdx.x * (int64_t)kBruteQueries;
+  const int64_t i = i0 + qloc;
   const bool live = i < n;
   const int me = live ? (int)(i < m ? i : m) : 0;
-  for (int k = 0; k < d; ++k) xq[t * d + k] = live ? locs[i * d + k] : 0.0;
+  for (int e = t; e < kBruteQueries * d; e += kQueryThreads) {
+    const int64_t iq = i0 + e / d;
+    xq[e] = (iq < n) ? locs[iq * d + e % d] : 0.0;
+  }
   int cnt = 0;
-  const int64_t jend = (i0 + kQueryThreads < n) ? i0 + kQueryThreads : n;  // candidates < jend
+  double wd = 0.0;
+  int32_t wj = 0;
+  const int64_t jend = (i0 + kBruteQueries < n) ? i0 + kBruteQueries : n;  // candidates < jend
   for (int64_t j0 = 0; j0 < jend; j0 += kQueryThreads) {
     const int64_t tn = (jend - j0 < kQueryThreads) ? jend - j0 : kQueryThreads;
     __syncthreads();
     for (int64_t e = t; e < tn * d; e += kQueryThreads) tile[e] = locs[j0 * d + e];
     __syncthreads();
     if (me > 0) {
-      for (int jj = 0; jj < (int)tn; ++jj) {
+      for (int jj = part; jj < (int)tn; jj += kBruteSplit) {
         const int64_t j = j0 + jj;
         if (j >= i) break;
         double d2 = 0.0;
         for (int k = 0; k < d; ++k) {
-          const double dz = tile[jj * d + k] - xq[t * d + k];
+          const double dz = tile[jj * d + k] - xq[qloc * d + k];
           d2 = fma(dz, dz, d2);
         }
-        if (cnt == me && !before(d2, (int32_t)j, bd(me - 1), bj(me - 1))) continue;
+        if (cnt == me && !before(d2, (int32_t)j, wd, wj)) continue;
         int q = (cnt < me) ? cnt : me - 1;
         while (q > 0 && before(d2, (int32_t)j, bd(q - 1), bj(q - 1))) {
           bd(q) = bd(q - 1);
@@ -240,13 +252,46 @@ __global__ __launch_bounds__(kQueryThreads) void brute_kernel(int64_t n, int d, 
         bd(q) = d2;
         bj(q) = (int32_t)j;
         if (cnt < me) ++cnt;
+        if (cnt == me) {
+          wd = bd(me - 1);
+          wj = bj(me - 1);
+        }
       }
     }
   }
-  if (live) {
+  cnts[t] = cnt;
+  __syncthreads();
+  if (live && part == 0) {
+    // merge the query's four sorted lists (disjoint candidate sets)
+    int pos[kBruteSplit], len[kBruteSplit];
+    for (int p = 0; p < kBruteSplit; ++p) {
+      pos[p] = 0;
+      len[p] = cnts[t + p];
+    }
     int32_t* row = NN + i * (int64_t)(m + 1);
     row[0] = (int32_t)i;
-    for (int q = 0; q < m; ++q) row[1 + q] = (q < cnt) ? bj(q) : -1;
+    for (int q = 0; q < m; ++q) {
+      int best = -1;
+      double bdist = 0.0;
+      int32_t bidx = 0;
+      for (int p = 0; p < kBruteSplit; ++p) {
+        if (pos[p] < len[p]) {
+          const double dp = bdv[pos[p] * kQueryThreads + t + p];
+          const int32_t jp = bjv[pos[p] * kQueryThreads + t + p];
+          if (best < 0 || before(dp, jp, bdist, bidx)) {
+            best = p;
+            bdist = dp;
+            bidx = jp;
+          }
+        }
+      }
+      if (q < me && best >= 0) {
+        row[1 + q] = bidx;
+        ++pos[best];
+      } else {
+        row[1 + q] = -1;
+      }
+    }
   }
 #undef bd
 #undef bj
@@ -441,10 +486,11 @@ int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t*
   if (!workspace || workspace_bytes < need) return VEC_EWORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (d > kMaxD) {
-    const unsigned nb = (unsigned)((n + kQueryThreads - 1) / kQueryThreads);
-    const size_t lds = ((size_t)2 * kQueryThreads * d + (size_t)(m > 0 ? m : 1) * kQueryThreads) *
+    const unsigned nb = (unsigned)((n + kBruteQueries - 1) / kBruteQueries);
+    const size_t lds = ((size_t)(kQueryThreads + kBruteQueries) * d +
+                        (size_t)(m > 0 ? m : 1) * kQueryThreads) *
                            sizeof(double) +
-                       (size_t)(m > 0 ? m : 1) * kQueryThreads * sizeof(int32_t);
+                       ((size_t)(m > 0 ? m : 1) + 1) * kQueryThreads * sizeof(int32_t);
     if (lds > 65536) {
       const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(brute_kernel),
                                                hipFuncAttributeMaxDynamicSharedMemorySize,
