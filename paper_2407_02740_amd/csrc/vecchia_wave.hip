@@ -73,7 +73,7 @@ __host__ __device__ inline Layout layout_of(int kmax, int dmax, int R, int p, in
   L.oZ = o;
   o += kmax * L.SZ;
   L.oV = o;
-  o += L.NR * L.SV;
+  o += (L.NR + 1) * L.SV;  // row NR: a sink for the stores of unused coordinates
   L.oG = o;
   o += L.NR * L.NR;
   L.oAcc = o;
@@ -93,6 +93,19 @@ __host__ __device__ inline Layout layout_of(int kmax, int dmax, int R, int p, in
 // LDS operations of one wave complete in program order, and a workgroup is
 // one wave: ordering them needs only a compiler fence.
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// The value itself, hidden from the optimiser at this point of the block
+// loop: comparisons of a per-coordinate or per-column index with it are then
+// made where they are used instead of being hoisted out of the loop and kept
+// live (as scalar masks) across every step.
+__device__ __forceinline__ int opaque_v(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+__device__ __forceinline__ int opaque_s(int x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
   const long long b = __double_as_longlong(x);
@@ -246,9 +259,10 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     // ---- gather: scaled coordinates (zero-padded to DMAX), y, X
     if (lane < kk) {
       const double* zs = a.locs + src * d;
+      const int dd = opaque_s(d);
       double z[DMAX];
 #pragma unroll
-      for (int k = 0; k < DMAX; ++k) z[k] = (k < d) ? zs[k] : 0.0;
+      for (int k = 0; k < DMAX; ++k) z[k] = (k < dd) ? zs[k] : 0.0;
 #pragma unroll
       for (int k = 0; k < DMAX; ++k) Z[lane * SZ + k] = z[k] * invrho[k];
       V[lane] = a.y[src];
@@ -298,24 +312,69 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
       double Ar[KMAX];
 #pragma unroll
       for (int cc = 0; cc < KMAX; ++cc) Ar[cc] = A[cc * SA + (lane < KMAX ? lane : 0)];
+      // Column cc's entries are broadcast CG at a time, each group's
+      // readlanes ahead of its updates.  Up to 48 rows the next pivot is
+      // taken, and its inverse square root started, right after the first
+      // group's updates, so that chain overlaps the rest of the column (at 64
+      // rows that longer code measured slower).
+      constexpr int CG = 4;
+      auto update = [&](double lrc, int s0) {
+        double b[CG];
 #pragma unroll
-      for (int cc = 0; cc < KMAX; ++cc) {
-        if (cc < kk) {  // columns past the neighbourhood are skipped whole
-          const double piv = readlane_d(Ar[cc], cc);
-          notpd = notpd || !(piv > 0.0);
-          const double inv = rsqrt_nr(piv);
-          const double lrc = Ar[cc] * inv;
-          Ar[cc] = lrc;
-          if (lane == 0) dinv[cc] = inv;
+        for (int q = 0; q < CG; ++q)
+          if (s0 + q < KMAX) b[q] = readlane_d(lrc, s0 + q);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int s = cc + 1; s < KMAX; ++s) Ar[s] = fma(-lrc, readlane_d(lrc, s), Ar[s]);
+        for (int q = 0; q < CG; ++q)
+          if (s0 + q < KMAX) Ar[s0 + q] = fma(-lrc, b[q], Ar[s0 + q]);
+      };
+      if constexpr (KMAX <= 48) {
+        double piv = readlane_d(Ar[0], 0);
+        double inv = rsqrt_nr(piv);
+        double myinv = 0.0;  // lane cc keeps 1 / L_cc,cc
+#pragma unroll
+        for (int cc = 0; cc < KMAX; ++cc) {
+          if (cc < kk) {  // columns past the neighbourhood are skipped whole
+            notpd = notpd || !(piv > 0.0);
+            const double lrc = Ar[cc] * inv;
+            Ar[cc] = lrc;
+            myinv = (lane == cc) ? inv : myinv;
+#pragma unroll
+            for (int s0 = cc + 1; s0 < KMAX; s0 += CG) {
+              update(lrc, s0);
+              if (s0 == cc + 1) {
+                piv = readlane_d(Ar[cc + 1], cc + 1);
+                inv = rsqrt_nr(piv);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        }
+        if (lane < kk) dinv[lane] = myinv;
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < KMAX; ++cc) {
+          if (cc < kk) {
+            const double piv = readlane_d(Ar[cc], cc);
+            notpd = notpd || !(piv > 0.0);
+            const double inv = rsqrt_nr(piv);
+            const double lrc = Ar[cc] * inv;
+            Ar[cc] = lrc;
+            if (lane == 0) dinv[cc] = inv;
+#pragma unroll
+            for (int s0 = cc + 1; s0 < KMAX; s0 += CG) {
+              update(lrc, s0);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
         }
       }
       // L transposed into the upper triangle: A[cc][r] = L_r,cc for cc <= r
       if (lane < kk) {
+        const int ln = opaque_v(lane);
 #pragma unroll
         for (int cc = 0; cc < KMAX; ++cc)
-          if (cc <= lane) A[cc * SA + lane] = Ar[cc];
+          if (cc <= ln) A[cc * SA + lane] = Ar[cc];
       }
     }
     if (notpd) {
@@ -329,22 +388,27 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     const int oU = 1 + p + R * g;
 
     WAVE_TMARK(3);
-    // ---- U = L^-T E_B by back substitution (lane r holds U[r][t])
+    // ---- U = L^-T E_B by back substitution (lane r holds U[r][t]); the
+    // next column's pivot factor and L entries are loaded one step ahead
     {
       double ub[GMAX];
 #pragma unroll
       for (int t = 0; t < GMAX; ++t) ub[t] = (lane == c + t) ? 1.0 : 0.0;
+      const int lrow = lane < KMAX ? lane : 0;
+      double dcn = dinv[kk - 1];
+      double lcn = A[lrow * SA + kk - 1];  // L[kk - 1][lane], used where lane < kk - 1
       for (int col = kk - 1; col >= 0; --col) {
-        const double dc = dinv[col];
-        const double lcl = (lane < col) ? A[lane * SA + col] : 0.0;  // L[col][lane]
+        const double dc = dcn, lcl = lcn;
+        if (col > 0) {
+          dcn = dinv[col - 1];
+          lcn = A[lrow * SA + col - 1];
+        }
 #pragma unroll
         for (int t = 0; t < GMAX; ++t) {
           if (t < g) {
             const double uc = readlane_d(ub[t], col) * dc;
-            if (lane < col)
-              ub[t] = fma(-lcl, uc, ub[t]);
-            else if (lane == col)
-              ub[t] = uc;
+            const double upd = fma(-lcl, uc, ub[t]);
+            ub[t] = (lane < col) ? upd : ((lane == col) ? uc : ub[t]);
           }
         }
       }
@@ -380,24 +444,32 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
 #pragma unroll
           for (int k = 0; k < DMAX; ++k) zn[k] = Z[b0 * SZ + k];
         }
+        // the pair factor and U entries of the next column are loaded one
+        // step ahead (the last step re-reads its own)
+        auto pairF = [&](int b) { return A[(b < r ? r : b) * SA + (b < r ? b : r)]; };
+        double Fn = pairF(b0), un[GMAX];
+#pragma unroll
+        for (int t = 0; t < GMAX; ++t) un[t] = V[(oU + t) * SV + b0];
         for (int b = b0; b < b1; ++b) {
+          const int bn = (b + 1 < b1) ? b + 1 : b;
           double zb[DMAX];
           if constexpr (kAhead) {
 #pragma unroll
             for (int k = 0; k < DMAX; ++k) zb[k] = zn[k];
-            const int bn = (b + 1 < b1) ? b + 1 : b;
 #pragma unroll
             for (int k = 0; k < DMAX; ++k) zn[k] = Z[bn * SZ + k];
           } else {
 #pragma unroll
             for (int k = 0; k < DMAX; ++k) zb[k] = Z[b * SZ + k];
           }
-          if (b == r) continue;
-          const int lo = b < r ? b : r, hi = b < r ? r : b;
-          const double F = A[hi * SA + lo];
+          // b == r adds nothing: its coordinate differences are exactly 0
+          const double F = (b == r) ? 0.0 : Fn;
           double cb[GMAX];
 #pragma unroll
-          for (int t = 0; t < GMAX; ++t) cb[t] = (t < g) ? F * V[(oU + t) * SV + b] : 0.0;
+          for (int t = 0; t < GMAX; ++t) cb[t] = (t < g) ? F * un[t] : 0.0;
+          Fn = pairF(bn);
+#pragma unroll
+          for (int t = 0; t < GMAX; ++t) un[t] = V[(oU + t) * SV + bn];
 #pragma unroll
           for (int k = 0; k < DMAX; ++k) {
             const double s = zr[k] - zb[k];
@@ -417,20 +489,28 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
 #pragma unroll
         for (int t = 0; t < GMAX; ++t) {
           if (t >= g) continue;
-          if (per_coord) {
+          // every 1 / rho_k is read before the first store
+          double ir[DMAX];
 #pragma unroll
-            for (int k = 0; k < DMAX; ++k)
-              if (k < d) V[(1 + p + k * g + t) * SV + r] = gs[k][t] * invrho[k];
-          } else {  // coordinates sharing a range add up
+          for (int k = 0; k < DMAX; ++k) ir[k] = invrho[k];
+          if (per_coord) {
+            // coordinates past d (zero sums) go to the sink row
+            const int dd = opaque_s(d);
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) {
+              const int row = (k < dd) ? 1 + p + k * g + t : Ly.NR;
+              V[row * SV + r] = gs[k][t] * ir[k];
+            }
+          } else {  // coordinates sharing a range add up (past d: zeros)
+            // coordinates before ns have the first range
+            const int ns = opaque_s(a.family == VEC_FAMILY_SPACETIME ? a.nspace : DMAX);
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int k = 0; k < DMAX; ++k) {
-              if (k < d) {
-                if (grp(k) == 0)
-                  s0 += gs[k][t] * invrho[k];
-                else
-                  s1 += gs[k][t] * invrho[k];
-              }
+              const double v = gs[k][t] * ir[k];
+              const bool first = k < ns;
+              s0 += first ? v : 0.0;
+              s1 += first ? 0.0 : v;
             }
             V[(1 + p + t) * SV + r] = s0;
             if (R > 1) V[(1 + p + g + t) * SV + r] = s1;
