@@ -689,13 +689,17 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     sfor<0, NS>([&](auto s_) { idg[s_.value] = 0.0; });
     bool notpd = false;
     double vself = 1.0;
+    // pivot of the next column: taken (and its reciprocal started) right
+    // after the first update group of the current one, so that chain runs
+    // under the remaining updates
+    double dv_next = bcast<G::lane_of(0)>(A[G::off(0) + 0]);
+    double ri_next = rcp_refined(dv_next);
     sfor<0, K>([&](auto c_) {
       constexpr int c = c_.value;
       constexpr int sc = c / 16;
-      constexpr int lc = G::lane_of(c);
-      const double dv = bcast<lc>(A[G::off(sc) + c]);
+      const double dv = dv_next;
       notpd |= !(dv > 0.0);
-      const double ri = rcp_refined(dv);
+      const double ri = ri_next;
       if constexpr (c == K - 1) vself = dv;
       idg[sc] = (row_of(sc, l) == c) ? ri : idg[sc];
       double Ls[NS];
@@ -703,16 +707,32 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         constexpr int s = s_.value;
         if constexpr (16 * s + 15 > c) Ls[s] = A[G::off(s) + c] * ri;
       });
-      sfor<c + 1, K>([&](auto r_) {
-        constexpr int r = r_.value;
-        constexpr int sr = r / 16;
-        constexpr int lr = G::lane_of(r);
-        const double arc = bcast<lr>(A[G::off(sr) + c]);
-        sfor<0, NS>([&](auto s_) {
-          constexpr int s = s_.value;
-          if constexpr (16 * s + 15 >= r)
-            A[G::off(s) + r] = __builtin_fma(-Ls[s], arc, A[G::off(s) + r]);
+      // rows c+1.. in groups of four: the group's broadcasts are issued
+      // ahead of its updates, into distinct registers, so no update waits on
+      // the broadcast just before it
+      sfor<0, (K - c + 2) / 4>([&](auto g_) {
+        constexpr int r0 = c + 1 + 4 * g_.value;
+        double arc[4];
+        sfor<0, 4>([&](auto q_) {
+          constexpr int r = r0 + q_.value;
+          if constexpr (r < K) arc[q_.value] = bcast<G::lane_of(r)>(A[G::off(r / 16) + c]);
         });
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<0, 4>([&](auto q_) {
+          constexpr int r = r0 + q_.value;
+          if constexpr (r < K) {
+            sfor<0, NS>([&](auto s_) {
+              constexpr int s = s_.value;
+              if constexpr (16 * s + 15 >= r)
+                A[G::off(s) + r] = __builtin_fma(-Ls[s], arc[q_.value], A[G::off(s) + r]);
+            });
+          }
+        });
+        if constexpr (g_.value == 0 && c + 1 < K) {
+          dv_next = bcast<G::lane_of(c + 1)>(A[G::off((c + 1) / 16) + c + 1]);
+          ri_next = rcp_refined(dv_next);
+        }
+        __builtin_amdgcn_sched_barrier(0);
       });
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
@@ -738,14 +758,18 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int NV = std::extent<std::remove_reference_t<decltype(x)>, 0>::value;
       constexpr int sc = c / 16;
       constexpr int lc = G::lane_of(c);
+      // every right-hand side's broadcast first, then the updates
+      double xc[NV];
+      sfor<0, NV>([&](auto v_) { xc[v_.value] = bcast<lc>(x[v_.value][sc]); });
+      __builtin_amdgcn_sched_barrier(0);
       sfor<0, NV>([&](auto v_) {
         constexpr int v = v_.value;
-        const double xc = bcast<lc>(x[v][sc]);
         sfor<0, NS>([&](auto s_) {
           constexpr int s = s_.value;
-          if constexpr (16 * s + 15 > c) x[v][s] = __builtin_fma(-A[G::off(s) + c], xc, x[v][s]);
+          if constexpr (16 * s + 15 > c) x[v][s] = __builtin_fma(-A[G::off(s) + c], xc[v], x[v][s]);
         });
       });
+      __builtin_amdgcn_sched_barrier(0);
     };
     auto fwd = [&](auto& x) { sfor<0, K>([&](auto c_) { fwd_step(c_, x); }); };
 
