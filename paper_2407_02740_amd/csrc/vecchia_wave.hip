@@ -41,6 +41,8 @@
 //               single-observation terms).
 #include <math.h>
 
+#include <type_traits>
+
 #include "vecchia.h"
 #include "vecchia_wave.hpp"
 
@@ -521,8 +523,47 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
     wave_fence();
 
     WAVE_TMARK(5);
-    // ---- L^-1 applied to every column (one column per lane)
-    if (lane < NR) {
+    // ---- L^-1 applied to every solved column.  With few columns (y, X and
+    // the derivative columns of one observation with one or two ranges) lanes
+    // are rows and the columns advance together, one factor column per step
+    // (right-looking); otherwise one column per lane.
+    auto row_solve = [&](auto nm_) {
+      constexpr int NM = decltype(nm_)::value;
+      const int lr = lane < KMAX ? lane : 0;
+      const int nr = opaque_s(NR);
+      double xv[NM];
+#pragma unroll
+      for (int j = 0; j < NM; ++j) xv[j] = (j < nr) ? V[j * SV + lr] : 0.0;
+      // the next step's pivot factor and L entries are loaded one step ahead
+      double dcn = dinv[0], lcn = A[lr];  // L[lane][0]
+      for (int col = 0; col < kk; ++col) {
+        const double dc = dcn, lcl = lcn;
+        if (col + 1 < kk) {
+          dcn = dinv[col + 1];
+          lcn = A[(col + 1) * SA + lr];  // L[lane][col + 1] where lane > col + 1
+        }
+        double xc[NM];
+#pragma unroll
+        for (int j = 0; j < NM; ++j) xc[j] = readlane_d(xv[j], col);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+          const double x = xc[j] * dc;
+          const double upd = fma(-lcl, x, xv[j]);
+          xv[j] = (lane > col) ? upd : ((lane == col) ? x : xv[j]);
+        }
+      }
+      if (lane < kk) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+          if (j < nr) V[j * SV + lane] = xv[j];
+      }
+    };
+    if (NR <= 4) {
+      row_solve(std::integral_constant<int, 4>{});
+    } else if (NR <= 6) {
+      row_solve(std::integral_constant<int, 6>{});
+    } else if (lane < NR) {  // one column per lane
       double* __restrict__ vj = V + lane * SV;
       double x[KMAX];
       // rows in blocks of 8, a block skipped as a whole once past kk (rows
