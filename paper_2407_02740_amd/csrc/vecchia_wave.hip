@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kLanes) void wave_kernel(const WaveArgs a) {
         if (lane == 0) flag(a.status, VEC_FLAG_BADNN, first > 0 ? first : 0);
         continue;
       }
-      g = (int)(last - first);
+      g = (GMAX == 1) ? 1 : (int)(last - first);  // GMAX == 1 serves gmax <= 1 only
       c = (int)(cend - cbase);
     } else {
       first = u;
