@@ -26,7 +26,8 @@
 //               lanes = rows, the g columns side by side).
 //   G_j         G_j = dSigma_j U for every range j (lanes = rows; the column
 //               loop split between the two half-waves when k <= 32).
-//   solves      L^-1 applied to y, X, every G_j and U (one column per lane).
+//   solves      L^-1 applied to y, X, every G_j and U (one column per lane;
+//               with at most six columns, lanes = rows).
 //   Gram        products of the solved columns over the conditioning rows.
 //   sums        with W_j = L^-1 dSigma_j U (W_sigma2 = E_B / sigma2,
 //               W_tau2 = sigma2 L^-1 U), z = L^-1 y, Z = L^-1 X and b, b'
