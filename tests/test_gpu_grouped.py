@@ -136,3 +136,29 @@ def test_malformed_blocks_and_empty_input():
     # no blocks: zero sums
     ev = V.GroupedVecchia(locs, y, X, [0], [0], [], 0, 0.5)
     assert float(ev.raw_sums(cp).abs().sum()) == 0.0
+
+
+def test_full_size_plane_sampled_blocks():
+    """The grouped benchmark problem at its full size (n = 262,144 points of
+    the plane, blocks of at most 4, m = 30, Matern 3/2), as the benchmark
+    groups it: the sums over two ranges of its blocks (the first ones, whose
+    conditioning sets are still short, and late ones), each launched like the
+    full problem (more blocks than the 8 workgroups per CU of the grid)."""
+    n, m, g = 262_144, 30, 4
+    rng = np.random.default_rng(21)
+    locs = rng.random((n, 2))
+    order, bs, cs, cond = S.group_cells(locs, g, m, seed=21)
+    pts = locs[order]
+    y = rng.standard_normal(n)
+    X = np.column_stack([np.ones(n), rng.standard_normal(n)])
+    cp = np.array((1.0, 0.05, 0.05))
+    nb = len(bs) - 1
+    for b0, b1 in ((0, 2200), (nb - 2300, nb)):
+        sbs = bs[b0:b1 + 1]
+        scs = cs[b0:b1 + 1] - cs[b0]
+        scond = cond[cs[b0]:cs[b1]]
+        _say(f"case blocks [{b0}, {b1}) of {nb}")
+        ev = V.GroupedVecchia(pts, y, X, sbs, scs, scond, 0, 1.5)
+        got = ev.raw_sums(cp).cpu().numpy()
+        ref = oracle.grouped_raw_sums(pts, y, X, cp, sbs, scs, scond, 0, 1.5)
+        check_raw(got, ref, 2, ev.P, f"blocks {b0}-{b1}")
