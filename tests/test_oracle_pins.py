@@ -87,6 +87,86 @@ def test_spacetime_reduces_to_isotropic_when_ranges_equal():
     np.testing.assert_allclose(dS1[1] + dS1[2], dS2[1], rtol=1e-12, atol=1e-15)
 
 
+# every split of d <= 4 coordinates into nspace leading spatial and d - nspace
+# temporal ones
+ST_SPLITS = [(2, 1), (3, 1), (3, 2), (4, 1), (4, 2), (4, 3)]
+
+
+def _st_scale(d, nspace, rho_s, rho_t):
+    return np.array([rho_s] * nspace + [rho_t] * (d - nspace))
+
+
+@pytest.mark.parametrize("d,nspace", ST_SPLITS)
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_spacetime_is_isotropic_on_rescaled_coordinates(d, nspace, nu):
+    # h^2 = |dz_space|^2 / rho_s^2 + |dz_time|^2 / rho_t^2: dividing the first
+    # nspace coordinates by rho_s and the others by rho_t gives the
+    # unit-range isotropic covariance (Section 4.3, Eq. 6 with the space-time
+    # reading of the "Jason-3 + Time" fit of Table 2).  The range derivatives
+    # are checked against central differences of that isotropic covariance
+    # with the rescaling of one group perturbed, so they never go through
+    # the space-time code.
+    rng = np.random.default_rng(30 + 7 * d + nspace)
+    locs = rng.random((11, d)) * np.array([1.0, 0.7, 1.3, 0.9])[:d]
+    s2, rs, rt, t2 = 1.3, 0.35, 1.9, 0.2
+    S1, dS1 = oracle.cov_matrix(locs, (s2, rs, rt, t2), ST, nu, nspace=nspace)
+
+    def iso(rho_s, rho_t):
+        return oracle.cov_matrix(locs / _st_scale(d, nspace, rho_s, rho_t), (s2, 1.0, t2), ISO,
+                                 nu)
+
+    S2, dS2 = iso(rs, rt)
+    np.testing.assert_allclose(S1, S2, rtol=1e-14)
+    np.testing.assert_allclose(dS1[0], dS2[0], rtol=1e-14)
+    np.testing.assert_allclose(dS1[3], dS2[2], rtol=1e-14)
+    for j, (a, b) in ((1, ((rs * (1 + 1e-6), rt), (rs * (1 - 1e-6), rt))),
+                      (2, ((rs, rt * (1 + 1e-6)), (rs, rt * (1 - 1e-6))))):
+        h = 2e-6 * (rs if j == 1 else rt)
+        fd = (iso(*a)[0] - iso(*b)[0]) / h
+        np.testing.assert_allclose(dS1[j], fd, rtol=1e-6, atol=1e-8, err_msg=f"range {j}")
+    # the two groups really differ: swapping the ranges changes the covariance
+    S3, _ = oracle.cov_matrix(locs, (s2, rt, rs, t2), ST, nu, nspace=nspace)
+    assert np.abs(S3 - S1).max() > 1e-3
+
+
+def _st_from_aniso(raw_an, p, d, nspace):
+    """Raw sums of the space-time family from those of the anisotropic family
+    at ranges (rho_s x nspace, rho_t x (d - nspace)): first derivatives
+    J^T d, information J^T I J with the chain-rule Jacobian J."""
+    P_an, P_st = d + 2, 4
+    J = np.zeros((P_an, P_st))
+    J[0, 0] = 1.0
+    J[1:1 + nspace, 1] = 1.0
+    J[1 + nspace:1 + d, 2] = 1.0
+    J[P_an - 1, 3] = 1.0
+    u = oracle.unpack_raw(raw_an, p, P_an)
+    return dict(logdet=u["logdet"], ySy=u["ySy"], XSX=u["XSX"], ySX=u["ySX"],
+                dlogdet=J.T @ u["dlogdet"], dySy=J.T @ u["dySy"],
+                dXSX=np.einsum("ja,jst->ast", J, u["dXSX"]),
+                dySX=np.einsum("ja,js->as", J, u["dySX"]), ainfo=J.T @ u["ainfo"] @ J)
+
+
+@pytest.mark.parametrize("d,nspace", ST_SPLITS)
+def test_spacetime_sums_equal_anisotropic_with_grouped_ranges(d, nspace):
+    # the space-time family is the anisotropic family with rho_k = rho_s on
+    # the spatial coordinates and rho_t on the temporal ones; its range
+    # derivatives are sums over the group's coordinates (chain rule)
+    rng = np.random.default_rng(40 + 7 * d + nspace)
+    n, m, p = 120, 8, 2
+    locs = rng.random((n, d))
+    locs = locs[S.maxmin_exact(locs)]
+    NN = S.find_ordered_nn(locs / _st_scale(d, nspace, 0.3, 1.4), m)
+    y = rng.standard_normal(n)
+    X = np.column_stack([np.ones(n), rng.standard_normal(n)])
+    cp_st = np.array([1.2, 0.3, 1.4, 0.07])
+    cp_an = np.concatenate([[1.2], _st_scale(d, nspace, 0.3, 1.4), [0.07]])
+    got = oracle.unpack_raw(oracle.raw_sums(locs, NN, y, X, cp_st, ST, 1.5, nspace=nspace), p, 4)
+    ref = _st_from_aniso(oracle.raw_sums(locs, NN, y, X, cp_an, AN, 1.5), p, d, nspace)
+    for key in ref:
+        np.testing.assert_allclose(got[key], ref[key], rtol=1e-11,
+                                   atol=1e-11 * (1 + np.max(np.abs(ref[key]))), err_msg=key)
+
+
 @pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
 def test_anisotropic_is_isotropic_on_rescaled_coordinates(nu):
     # Eq. 6 with a range per coordinate: dividing coordinate k by rho_k
