@@ -91,6 +91,51 @@ def profiled_traffic():
         return None
 
 
+def host_cpu():
+    """(CPU model, logical CPUs the OS reports, threads this job may use).
+    The oracle's all-core leg uses the CPUs this process may run on, at most
+    16 (the host share of one GPU)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, max(1, min(16, avail))
+
+
+def oracle_baseline(w, sample_all: int, sample_one: int, what: str) -> dict:
+    """The CPU oracle timed on the last `sample_all` neighbourhoods with every
+    thread this job may use and on the last `sample_one` with one thread
+    (the paper's 1-core / multi-core framing of its CPU baseline)."""
+    import oracle
+
+    oracle.build()
+    model, nproc, threads = host_cpu()
+    n = w["n"]
+    rates = {}
+    for nt, S_ in ((threads, min(sample_all, n)), (1, min(sample_one, n))):
+        log(f"CPU oracle on observations [{n - S_}, {n}) with {nt} thread(s)")
+        tc = time.perf_counter()
+        oracle.raw_sums(w["locs"], w["NN"], w["y"], w["X"], w["covparms"], w["family"], w["nu"],
+                        w["nspace"], i0=n - S_, i1=n, threads=nt)
+        rates[nt] = (S_ / (time.perf_counter() - tc), S_, time.perf_counter() - tc)
+        log(f"CPU oracle, {nt} thread(s): {rates[nt][0]:.4e} nbhd/s")
+    v, S_all, t_all = rates[threads]
+    v1, S_one, t_one = rates[1]
+    return {"value": v, "unit": "neighbourhoods/s", "cores": threads, "kind": "oracle",
+            "sample": f"last {S_all} of {n} neighbourhoods ({what}) on {threads} threads, "
+                      f"{t_all:.2f} s wall; last {S_one} on 1 thread, {t_one:.2f} s wall",
+            "value_1core": v1, "nproc": nproc, "cpu_model": model}
+
+
 def calibration_kernel():
     """A kernel of known HBM traffic for scaling the FETCH_SIZE / WRITE_SIZE
     counters: an in-place multiply of 512 MiB reads and writes 512 MiB."""
@@ -110,6 +155,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=524_288)
+    ap.add_argument("--cpu-sample-1core", type=int, default=65_536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibration", action="store_true",
                     help="also run a kernel of known traffic (512 MiB read + 512 MiB write) "
@@ -227,20 +273,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-
-        oracle.build()
-        threads = min(16, os.cpu_count() or 1)
-        S_ = min(args.cpu_sample, n)
-        log(f"CPU oracle on observations [{n - S_}, {n}) with {threads} threads")
-        tc = time.perf_counter()
-        oracle.raw_sums(w["locs"], w["NN"], w["y"], w["X"], w["covparms"], w["family"], w["nu"],
-                        w["nspace"], i0=n - S_, i1=n, threads=threads)
-        dtc = time.perf_counter() - tc
-        cpu = {"value": S_ / dtc, "unit": "neighbourhoods/s", "cores": threads, "kind": "oracle",
-               "sample": f"last {S_} of {n} neighbourhoods (m=30) of the same workload, "
-                         f"{dtc:.2f} s wall"}
-        log(f"CPU oracle {cpu['value']:.4e} nbhd/s")
+        cpu = oracle_baseline(w, args.cpu_sample, args.cpu_sample_1core,
+                              "m=30, same workload")
 
     line = {
         "metric": METRIC, "value": value, "unit": "neighbourhoods/s", "n_gpus": 1,

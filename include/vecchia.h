@@ -100,6 +100,12 @@ typedef struct {
   int32_t nspace;    /* space-time: leading spatial coordinates, 1..d-1    */
   int32_t reserved;  /* must be 0                                          */
 } vec_problem;
+/* Space-time split.  With nspace = d - 1 (time the last coordinate) every
+ * entry point accepts VEC_FAMILY_SPACETIME.  Any other split runs on the
+ * kernel that gives each neighbourhood a whole wave, so it is accepted
+ * where VEC_FAMILY_ANISO is (vec_raw_sums, vec_block_sums, vec_combine,
+ * vecchia_loglik_grad_info, vec_fisher_update, vec_fisher_fit, m <= 63);
+ * the other entry points return VEC_EINVAL for it. */
 
 /* Number of covariance parameters P, raw sums, and combined outputs; a
  * negative return means the problem description is invalid. */
@@ -206,7 +212,8 @@ int vec_kriging_weights(const vec_problem* pb, const double* locs, const int32_t
  * prediction points appended to locs, y and X (y of a prediction point is
  * ignored; pass 0).  NN_pred holds only the prediction rows: row j (point
  * n_obs + j) is [n_obs + j, its m nearest observed points (indices <
- * n_obs)], m + 1 int32 per row.  With betahat the mean parameters (e.g. the
+ * n_obs)], m + 1 int32 per row; an index outside [0, n_obs), e.g. another
+ * prediction point, sets VEC_FLAG_BADNN with that point's index.  With betahat the mean parameters (e.g. the
  * GLS estimate of vec_loglik):
  *   mean[j] = x_j betahat + c' Sigma_s^-1 (y_s - X_s betahat),
  *   var[j]  = Sigma_jj - c' Sigma_s^-1 c   (the observation process, nugget

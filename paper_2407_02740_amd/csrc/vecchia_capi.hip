@@ -78,6 +78,12 @@ static bool dims_of(const vec_problem* pb, Dims* dm) {
   } else if (pb->family == VEC_FAMILY_SPACETIME) {
     if (pb->d > 4 || pb->nspace < 1 || pb->nspace >= pb->d) return false;
     dm->P = 4;
+    // the fused kernel scales the last coordinate alone by rho_t; any other
+    // split of the coordinates runs on the wave kernel
+    if (pb->nspace != pb->d - 1) {
+      if (pb->m + 1 > vecchia_wave::kMaxK) return false;
+      dm->wave = true;
+    }
   } else if (pb->family == VEC_FAMILY_ANISO) {
     if (pb->d > vecchia_wave::kMaxD || pb->m + 1 > vecchia_wave::kMaxK) return false;
     dm->P = pb->d + 2;

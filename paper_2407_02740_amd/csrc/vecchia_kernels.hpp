@@ -345,17 +345,20 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
 
   // Neighbour indices of observation ii for this lane's rows: id = -1 for
   // padding rows (and rows >= K), ii for the self row.  Only valid columns
-  // 1..q of the NNarray row are read (column 0 otherwise).
+  // 1..q of the NNarray row are read (column 0 otherwise).  Neighbours are
+  // earlier observations; rows appended after the observed ones (nn_row0 >
+  // 0, prediction points) may only name observed points j < nn_row0.
   auto fetch_ids = [&](int64_t ii, int lan, int64_t(&id)[NS], bool& bad) {
     const int qq = (int)(ii < (int64_t)m ? ii : (int64_t)m);
     const int32_t* row = NN + (ii - a.nn_row0) * (int64_t)(m + 1);
+    const int64_t jend = (a.nn_row0 > 0) ? a.nn_row0 : ii;
     bad = (row[0] != (int32_t)ii);
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, lan);
       const bool nb = r < qq;
       const int64_t j = row[nb ? 1 + r : 0];
-      const bool okj = (j >= 0) && (j < ii);
+      const bool okj = (j >= 0) && (j < jend);
       bad = bad || (nb && !okj);
       id[s] = (r == K - 1) ? ii : ((nb && okj) ? j : (int64_t)-1);
     });

@@ -162,7 +162,7 @@ class Vecchia:
     by the library entry points on the current torch stream."""
 
     def __init__(self, locs, NN, y, X, family: int = FAMILY_ISO, smoothness: float = 0.5,
-                 nspace: int = 0, device: str = "cuda"):
+                 nspace: int = 0, device: str = "cuda", _check_rows: bool = True):
         def f64(a):
             return torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
 
@@ -175,6 +175,13 @@ class Vecchia:
         if self.X.dim() == 1:
             self.X = self.X[:, None].contiguous()
         n, d = self.locs.shape
+        # shapes are checked here: the kernels read NN, y and X by these sizes
+        if self.NN.dim() != 2 or self.NN.shape[1] < 1 or (_check_rows and self.NN.shape[0] != n):
+            raise ValueError(f"NN must be [n = {n}][m + 1], got {tuple(self.NN.shape)}")
+        if self.y.shape != (n,):
+            raise ValueError(f"y must be [n = {n}], got {tuple(self.y.shape)}")
+        if self.X.dim() != 2 or self.X.shape[0] != n:
+            raise ValueError(f"X must be [n = {n}][p], got {tuple(self.X.shape)}")
         self.pb = Problem(n=n, m=self.NN.shape[1] - 1, d=d, p=self.X.shape[1], family=family,
                           smoothness=float(smoothness), nspace=int(nspace), reserved=0)
         L = lib()
@@ -203,10 +210,25 @@ class Vecchia:
         return self._ws
 
     def covparms(self, covparms) -> torch.Tensor:
+        """covparms as a contiguous FP64 device tensor of P entries: a device
+        tensor that already is one is passed through (no copy), anything else
+        is copied to the device."""
+        if isinstance(covparms, torch.Tensor) and covparms.is_cuda:
+            if covparms.numel() != self.P:
+                raise ValueError(f"covparms needs {self.P} entries, got {covparms.numel()}")
+            _dev(covparms, torch.float64, "covparms")
+            return covparms
         t = torch.as_tensor(covparms, dtype=torch.float64).to(self.device).contiguous()
         if t.numel() != self.P:
             raise ValueError(f"covparms needs {self.P} entries")
         return t
+
+    def _inplace_cp(self, covparms) -> torch.Tensor:
+        # parameters updated in place on the device: must already be a
+        # device tensor of P entries
+        if not (isinstance(covparms, torch.Tensor) and covparms.is_cuda):
+            raise TypeError("covparms must be a device tensor (updated in place)")
+        return self.covparms(covparms)
 
     def clear_status(self):
         _check(lib().vec_status_clear(_dev(self.status, torch.int32, "status"), _stream()),
@@ -222,8 +244,7 @@ class Vecchia:
     # -- entry points ---------------------------------------------------------
     def raw_sums(self, covparms, i0: int = 0, i1: int | None = None, check: bool = True):
         i1 = self.n if i1 is None else i1
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         ws = self.workspace(i0, i1)
         _check(lib().vec_raw_sums(ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(),
                                   self.y.data_ptr(), self.X.data_ptr(),
@@ -248,8 +269,7 @@ class Vecchia:
         return nb.value
 
     def loglik_grad_info(self, covparms, check: bool = True):
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         ws = self.workspace()
         _check(lib().vecchia_loglik_grad_info(
             ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
@@ -263,8 +283,7 @@ class Vecchia:
     def loglik(self, covparms, check: bool = True) -> torch.Tensor:
         """Profile log-likelihood alone (the sums of Algorithm 1 and the
         combine step): a new tensor [loglik, betahat[p], betainfo[p][p]]."""
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         ws = self.workspace()
         out = torch.empty(1 + self.p + self.p * self.p, dtype=torch.float64, device=self.device)
         _check(lib().vec_loglik(
@@ -281,8 +300,7 @@ class Vecchia:
         """Reverse-mode gradient of the log-likelihood at the mean vector
         betahat, each neighbourhood's factor recomputed: returns new tensors
         (loglik at betahat, grad_out * d loglik / d covparms)."""
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         beta = torch.as_tensor(betahat, dtype=torch.float64).to(self.device).contiguous()
         if beta.numel() != self.p:
             raise ValueError(f"betahat needs {self.p} entries")
@@ -308,8 +326,7 @@ class Vecchia:
         (NNarray column order) and log conditional variance in correlation
         units, [i1 - i0][m + 1] FP64; self.raw receives the loglik sums."""
         i1 = self.n if i1 is None else i1
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         m1 = self.pb.m + 1
         if out is None:
             out = torch.empty(max(i1 - i0, 0), m1, dtype=torch.float64, device=self.device)
@@ -326,6 +343,7 @@ class Vecchia:
         return out
 
     def fisher_update(self, covparms: torch.Tensor, max_step: float = 1.0):
+        covparms = self._inplace_cp(covparms)
         _check(lib().vec_fisher_update(ctypes.byref(self.pb), self.out.data_ptr(),
                                        _dev(covparms, torch.float64, "covparms"),
                                        self.status.data_ptr(), float(max_step), _stream()),
@@ -334,6 +352,7 @@ class Vecchia:
 
     def fisher_fit(self, covparms: torch.Tensor, iters: int, use_graph: bool = True,
                    max_step: float = 1.0, check: bool = True):
+        covparms = self._inplace_cp(covparms)
         ws = self.workspace()
         _check(lib().vec_fisher_fit(
             ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
@@ -401,7 +420,8 @@ class GroupedVecchia(Vecchia):
         self.nblocks = len(bs) - 1
         n = len(np.asarray(y))
         dummy_nn = np.zeros((1, m + 1), dtype=np.int32)
-        super().__init__(locs, dummy_nn, y, X, family, smoothness, nspace, device)
+        super().__init__(locs, dummy_nn, y, X, family, smoothness, nspace, device,
+                         _check_rows=False)
         self.pb.n = n
         self.n = n
         self.block_start = torch.as_tensor(bs, device=self.device)
@@ -423,8 +443,7 @@ class GroupedVecchia(Vecchia):
                 self.cond.data_ptr(), self.ncond, self.max_block)
 
     def raw_sums(self, covparms, i0: int = 0, i1: int | None = None, check: bool = True):
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         ws = self.workspace()
         _check(lib().vec_grouped_raw_sums(
             ctypes.byref(self.pb), self.locs.data_ptr(), self.y.data_ptr(), self.X.data_ptr(),
@@ -446,6 +465,7 @@ class GroupedVecchia(Vecchia):
     def fisher_fit(self, covparms: torch.Tensor, iters: int, use_graph: bool = True,
                    max_step: float = 1.0, check: bool = True):
         ws = self.workspace()
+        covparms = self._inplace_cp(covparms)
         _check(lib().vec_grouped_fisher_fit(
             ctypes.byref(self.pb), self.locs.data_ptr(), self.y.data_ptr(), self.X.data_ptr(),
             _dev(covparms, torch.float64, "covparms"), *self._blocks(), int(iters),
@@ -487,8 +507,7 @@ class Predictor:
 
     def predict(self, covparms, betahat, check: bool = True):
         ev = self.ev
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            ev.covparms(covparms)
+        cp = ev.covparms(covparms)
         beta = torch.as_tensor(betahat, dtype=torch.float64).to(ev.device).contiguous()
         mean = torch.empty(self.n_pred, dtype=torch.float64, device=ev.device)
         var = torch.empty_like(mean)
@@ -631,6 +650,9 @@ class VecchiaBatch:
         if self.X.dim() == 1:
             self.X = self.X[:, None].contiguous()
         nsets = len(n)
+        if self.y.dim() != 1 or self.X.shape[0] != self.locs.shape[0] or \
+                self.y.shape[0] != self.locs.shape[0]:
+            raise ValueError("locs, y and X must have the same number of rows")
         self.nsets = nsets
         self.sets = (Dataset * nsets)()
         for b in range(nsets):
@@ -675,6 +697,11 @@ class VecchiaBatch:
         return self.plan
 
     def covparms(self, covparms) -> torch.Tensor:
+        if isinstance(covparms, torch.Tensor) and covparms.is_cuda:
+            if covparms.numel() != self.nsets * self.P:
+                raise ValueError(f"covparms must be [{self.nsets}][{self.P}]")
+            _dev(covparms, torch.float64, "covparms")
+            return covparms
         t = torch.as_tensor(covparms, dtype=torch.float64).to(self.device).contiguous()
         if t.shape != (self.nsets, self.P):
             raise ValueError(f"covparms must be [{self.nsets}][{self.P}]")
@@ -701,8 +728,7 @@ class VecchiaBatch:
                 _dev(cp, torch.float64, "covparms"))
 
     def raw_sums(self, covparms, check: bool = True):
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         _check(_batch_lib().vec_batch_raw_sums(*self._args(cp), self.raw.data_ptr(),
                                                self._ws.data_ptr(), self._ws.numel() * 8,
                                                self.status.data_ptr(), _stream()),
@@ -712,8 +738,7 @@ class VecchiaBatch:
         return self.raw
 
     def loglik_grad_info(self, covparms, check: bool = True):
-        cp = covparms if isinstance(covparms, torch.Tensor) and covparms.is_cuda else \
-            self.covparms(covparms)
+        cp = self.covparms(covparms)
         _check(_batch_lib().vec_batch_loglik_grad_info(
             *self._args(cp), self.raw.data_ptr(), self.out.data_ptr(), self._ws.data_ptr(),
             self._ws.numel() * 8, self.status.data_ptr(), _stream()),
@@ -724,6 +749,9 @@ class VecchiaBatch:
 
     def fisher_fit(self, covparms: torch.Tensor, iters: int, use_graph: bool = True,
                    max_step: float = 1.0, check: bool = True):
+        if not (isinstance(covparms, torch.Tensor) and covparms.is_cuda):
+            raise TypeError("covparms must be a device tensor (updated in place)")
+        covparms = self.covparms(covparms)
         _check(_batch_lib().vec_batch_fisher_fit(
             *self._args(covparms), int(iters), float(max_step), self.raw.data_ptr(),
             self.out.data_ptr(), self._ws.data_ptr(), self._ws.numel() * 8,
