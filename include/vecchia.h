@@ -158,6 +158,25 @@ int vecchia_loglik_grad_info(const vec_problem* pb, const double* locs, const in
                          double* out, void* workspace, size_t workspace_bytes, int32_t* status,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * vecchia_loglik_grad_info without the workspace argument.  The partial sums
+ * go to a 2 MiB array of device memory inside the library, one per device,
+ * reserved when the library's code is loaded on that device and held until
+ * the process ends; its address is looked up once per device on the first
+ * call.  The call allocates nothing and runs the same kernels, so raw and
+ * out equal those of vecchia_loglik_grad_info bit for bit.  Problems whose
+ * partial sums need more than 2 MiB (vec_workspace_bytes(pb, 0, n) > 2 MiB:
+ * only families with many parameters, e.g. VEC_FAMILY_ANISO at large d)
+ * return VEC_EWORKSPACE before anything is enqueued.  Every call on a device
+ * shares that device's array: calls that overlap in time on one device
+ * (different streams, or different host threads) race and give undefined
+ * results; calls ordered on one stream are safe. */
+int vecchia_loglik_grad_info_noalloc(const vec_problem* pb, const double* locs,
+                                     const int32_t* NNarray, const double* y, const double* X,
+                                     const double* covparms, double* raw, double* out,
+                                     int32_t* status, void* stream);
+
 /* The profile log-likelihood alone: the sums of Algorithm 1 (Section 3)
  * without the derivative and information work, then the combine step.
  * raw receives [logdet, ySy, XSX[p][p], ySX[p]] (the first 2 + p*p + p

@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <vector>
 
 #include "vecchia.h"
@@ -756,6 +757,37 @@ static int enqueue_grouped_sums(const vec_problem* pb, const Dims& dm, const dou
 
 using namespace vecchia;
 
+// ----------------------------------------------------------------------------
+// device scratch of the allocation-free entry point
+// ----------------------------------------------------------------------------
+
+// Partial sums of vecchia_loglik_grad_info_noalloc: one copy per device,
+// held from the library's first use on that device until the process ends.
+// Host code never names the array in a kernel argument or a copy: the name
+// is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)2 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device.
+static int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VEC_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return VEC_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return VEC_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return VEC_OK;
+}
+
 extern "C" {
 
 int vec_nparms(const vec_problem* pb) {
@@ -826,6 +858,28 @@ int vecchia_loglik_grad_info(const vec_problem* pb, const double* locs, const in
                         workspace_bytes, status, stream);
   if (rc != VEC_OK) return rc;
   return vec_combine(pb, raw, out, status, stream);
+}
+
+int vecchia_loglik_grad_info_noalloc(const vec_problem* pb, const double* locs,
+                                     const int32_t* NNarray, const double* y, const double* X,
+                                     const double* covparms, double* raw, double* out,
+                                     int32_t* status, void* stream) {
+  Dims dm;
+  if (!dims_of(pb, &dm)) return VEC_EINVAL;
+  if (!locs || !NNarray || !y || !X || !covparms || !raw || !out || !status) return VEC_EINVAL;
+  // every workgroup writes its whole row of partials, so nothing in the
+  // scratch array has to start at zero
+  const size_t need = vec_workspace_bytes(pb, 0, pb->n);
+  if (need > kScratchBytes) return VEC_EWORKSPACE;
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc != VEC_OK) return rc;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const int rs = enqueue_sums(pb, dm, kModeSums, locs, NNarray, y, X, covparms, nullptr, 0, pb->n,
+                              raw, ws, kScratchBytes, status, st);
+  if (rs != VEC_OK) return rs;
+  enqueue_combine(pb, dm, raw, out, status, st);
+  return hip_code(hipGetLastError());
 }
 
 int vec_loglik(const vec_problem* pb, const double* locs, const int32_t* NNarray, const double* y,

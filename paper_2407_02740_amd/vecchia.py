@@ -70,6 +70,9 @@ def lib():
         L.vecchia_loglik_grad_info.restype = ctypes.c_int
         L.vecchia_loglik_grad_info.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                            ctypes.c_size_t, _VP, _VP]
+        L.vecchia_loglik_grad_info_noalloc.restype = ctypes.c_int
+        L.vecchia_loglik_grad_info_noalloc.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                                       _VP]
         L.vec_loglik.restype = ctypes.c_int
         L.vec_loglik.argtypes = [pp, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP,
                                  _VP]
@@ -278,6 +281,19 @@ class Vecchia:
             "vecchia_loglik_grad_info")
         if check:
             self.check_status("vecchia_loglik_grad_info")
+        return self.out
+
+    def loglik_grad_info_noalloc(self, covparms, check: bool = True):
+        """loglik_grad_info through the entry point that allocates nothing:
+        the library's own per-device scratch array replaces the workspace."""
+        cp = self.covparms(covparms)
+        _check(lib().vecchia_loglik_grad_info_noalloc(
+            ctypes.byref(self.pb), self.locs.data_ptr(), self.NN.data_ptr(), self.y.data_ptr(),
+            self.X.data_ptr(), _dev(cp, torch.float64, "covparms"), self.raw.data_ptr(),
+            self.out.data_ptr(), self.status.data_ptr(), _stream()),
+            "vecchia_loglik_grad_info_noalloc")
+        if check:
+            self.check_status("vecchia_loglik_grad_info_noalloc")
         return self.out
 
     def loglik(self, covparms, check: bool = True) -> torch.Tensor:
