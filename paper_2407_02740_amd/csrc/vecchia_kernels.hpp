@@ -68,6 +68,7 @@
 namespace vecchia {
 
 #include "exp_table.inc"
+#include "dpp_fmac.inc"
 
 #ifdef VECCHIA_ISA_MARKS
 #define VEC_MARK(x) asm volatile(";@@ " x)
@@ -181,6 +182,21 @@ struct Geo {
   }
   static constexpr int NL = off(NS);
   static constexpr int slot_of(int r) { return r / 16; }
+  // Factorisation column c updates rows c+1..K-1 in groups of up to four
+  // rows that lie in one 16-row block: first row of group g, group count.
+  static constexpr int gstart(int c, int g) {
+    int r = c + 1;
+    for (int t = 0; t < g && r < K; ++t) {
+      const int bend = (16 * (r / 16 + 1) < K) ? 16 * (r / 16 + 1) : K;
+      r += (bend - r < 4) ? bend - r : 4;
+    }
+    return r;
+  }
+  static constexpr int ngroups(int c) {
+    int g = 0;
+    while (gstart(c, g) < K) ++g;
+    return g;
+  }
   static constexpr int lane_of(int r) {
     return ((r / 16) & 1) ? 16 * (r / 16) + 15 - r : r - 16 * (r / 16);
   }
@@ -194,14 +210,16 @@ __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOM
 
 __device__ __forceinline__ int row_of(int s, int l) { return 16 * s + ((s & 1) ? 15 - l : l); }
 
-// h = sqrt(h2) and 1/h.  1e-300 is added to h2 so that coincident
-// locations give h ~ 1e-150 and a finite 1/h (every use multiplies 1/h by a
-// squared coordinate difference that is then 0); for any h2 above 1e-284 the
-// addition does not change h2.
+// Squared distances are accumulated from kH2Floor instead of 0, so that
+// coincident locations give h ~ 1e-150 and a finite 1/h (every use
+// multiplies 1/h by a squared coordinate difference that is then 0); for any
+// h2 above 1e-284 the floor does not change the sum.
+constexpr double kH2Floor = 1e-300;
+
+// h = sqrt(h2) and 1/h for h2 >= kH2Floor.
 __device__ __forceinline__ void dist_from_sq(double h2, double& h, double& hinv) {
-  const double x = h2 + 1e-300;
-  const double r = rsqrt_refined(x);
-  h = x * r;
+  const double r = rsqrt_refined(h2);
+  h = h2 * r;
   hinv = r;
 }
 
@@ -210,6 +228,11 @@ struct CovCoef {
   double c1, c2;        // f = (1 + c1 h + c2 h^2) e^-h
   double a0, a1, a2;    // -f'(h)/h = (a0 + a1 h + a2/h) e^-h
   double ir[2];         // 1/range per group
+  // gather: scaled coordinate k of a row is locs[row][col[k]] * sc[k]
+  // (isotropic: coordinate k, zero beyond d; space-time: spatial
+  // coordinates 0..d-2 in z[0..d-2], time coordinate d-1 in z[3])
+  int col[4];
+  double sc[4];
 };
 
 // Batched launches.  The device plan holds, per dataset, kSetFields int64:
@@ -284,7 +307,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   constexpr int RZ = 0, RU = 4;
   constexpr int RS = 6;  // row stride, 16-byte aligned
   __shared__ double rec[kGroupsPerBlock][KP][RS];
-  __shared__ double Lp[kGroupsPerBlock][kLik ? 1 : LPN + 16];  // + one write sink per lane
+  // rows 0..K-1 packed at r(r-1)/2 (stores of a row run past its diagonal
+  // into later rows, see the store below), then a sink for rows >= K
+  constexpr int LPS = LPN + 1 + K;
+  __shared__ double Lp[kGroupsPerBlock][kLik ? 1 : LPS];
   __shared__ double acc[kGroupsPerBlock][NRAW];
   // running product of conditional variances (mantissa, exponent)
   __shared__ double vprod[kGroupsPerBlock][2];
@@ -297,6 +323,14 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
   constexpr double kFar = 1e30;
+  // Lp offsets of this lane's rows: where its row r starts (the sink for
+  // rows >= K), and its column r in the rows below
+  int lrow_base[NS], lcol_base[NS];
+  sfor<0, NS>([&](auto s_) {
+    const int r = row_of(s_.value, lane);
+    lrow_base[s_.value] = (r < K) ? r * (r - 1) / 2 : LPN + 1;
+    lcol_base[s_.value] = r;
+  });
 
   // the problem of the current tile (BATCH: one dataset's slice)
   const int d = a.d;
@@ -309,6 +343,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   int32_t* __restrict__ status = a.status;
   int64_t i0 = a.i0, total = a.i1 - a.i0;
 
+  __shared__ double exptab[64];
   CovCoef cf;
   double inv_sigma2;
   double bt[PC];
@@ -325,14 +360,26 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     cf.a2 = (nu == 0) ? 1.0 : 0.0;
     inv_sigma2 = 1.0 / cf.sigma2;
 #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (NG == 2 && k == 3) {
+        cf.col[k] = d - 1;
+        cf.sc[k] = cf.ir[1];
+      } else {
+        const int dl = (NG == 2) ? d - 1 : d;  // coordinates scaled by the first range
+        cf.col[k] = (k < dl) ? k : dl - 1;
+        cf.sc[k] = (k < dl) ? cf.ir[0] : 0.0;
+      }
+    }
+#pragma unroll
     for (int t = 0; t < PC; ++t) bt[t] = kAdj ? a.beta[t] : 0.0;
+    // 2^(j/64) scaled by sigma2: every covariance entry carries the factor
+    exptab[threadIdx.x] = kExp2Tab[threadIdx.x] * cf.sigma2;
+    wave_lds_fence();
   };
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
   if (kStoreF && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
-  __shared__ double exptab[64];
   static_assert(kThreads == 64, "one table entry per thread");
-  exptab[threadIdx.x] = kExp2Tab[threadIdx.x];
   __syncthreads();
   if (threadIdx.x < kGroupsPerBlock) {
     vprod[threadIdx.x][0] = 1.0;
@@ -370,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int s = s_.value;
       const int64_t ids = (id[s] >= 0) ? id[s] : ii;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) zv[s][k] = (k < d) ? locs[ids * d + k] : 0.0;
+      for (int k = 0; k < 4; ++k) zv[s][k] = locs[ids * d + cf.col[k]];
       yv[s] = y[ids];
 #pragma unroll
       for (int t = 0; t < PC; ++t) xv[s][t] = X[ids * PC + t];
@@ -487,21 +534,12 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int s = s_.value;
       const int r = row_of(s, l);
       const bool has = idc[s] >= 0;
-      // isotropic: coordinate k in z[k]; space-time: spatial coordinates
-      // 0..d-2 in z[0..d-2] scaled by 1/rho_s, time (coordinate d-1) in z[3]
-      // scaled by 1/rho_t
-      double zc[4] = {0.0, 0.0, 0.0, 0.0};
+      // scaled coordinates (the column map of set_params); a non-finite
+      // coordinate makes the sum non-finite
+      double zc[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k < d) {
-          const double v = zv[s][k];
-          badval |= has && !__builtin_isfinite(v);
-          if (NG == 2 && k == d - 1)
-            zc[3] = v * cf.ir[1];
-          else
-            zc[k] = v * cf.ir[0];
-        }
-      }
+      for (int k = 0; k < 4; ++k) zc[k] = zv[s][k] * cf.sc[k];
+      badval |= has && !__builtin_isfinite((zc[0] + zc[1]) + (zc[2] + zc[3]));
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         zo[s][k] = has ? zc[k] : ((k == 0) ? kFar * (double)(1 + r) : 0.0);
@@ -527,12 +565,12 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // that their latencies overlap), and each pair's range-derivative factor
     // sigma2 (-f'(h)/h) stored at sfv[idx].  exp(-h) is table driven: with
     // -h = (64 m + j) ln2/64 + r, |r| <= ln2/128,
-    //   e^-h = 2^m * T[j] * (1 + q),  T[j] = 2^(j/64),
+    //   sigma2 e^-h = 2^m * T[j] * (1 + q),  T[j] = sigma2 2^(j/64),
     //   q = r + r^2/2 + ... + r^5/120 (truncation below 4e-17 relative),
     // formed as T + T q; -h is clamped at -800 so that 2^m underflows to 0.
     auto pair_eval2 = [&](const double* za0, const double* zb0, int idx0, const double* za1,
                           const double* zb1, int idx1, double& v0, double& v1) {
-      double h20 = 0.0, h21 = 0.0;
+      double h20 = kH2Floor, h21 = kH2Floor;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double t0 = za0[k] - zb0[k];
@@ -559,8 +597,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       q1 = __builtin_fma(q1, r1, 1.0);
       q0 *= r0;
       q1 *= r1;
-      const double sE0 = cf.sigma2 * ldexp(__builtin_fma(T0, q0, T0), i0n >> 6);
-      const double sE1 = cf.sigma2 * ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
+      const double sE0 = ldexp(__builtin_fma(T0, q0, T0), i0n >> 6);
+      const double sE1 = ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
       const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
       const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
       if constexpr (kStoreF) {
@@ -692,10 +730,36 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     sfor<0, NS>([&](auto s_) { idg[s_.value] = 0.0; });
     bool notpd = false;
     double vself = 1.0;
+    // One group of column c's updates: rows r0 .. r0+n-1 of block b, then
+    // the next group.  After the first group the next column's pivot is
+    // broadcast and its reciprocal started, so that chain runs under the
+    // remaining updates.
+    auto chol_group = [&](auto c_, auto r0_, auto nL_, double& dvn, double& rin) {
+      constexpr int c = decltype(c_)::value, r0 = decltype(r0_)::value;
+      constexpr int b = r0 / 16;
+      constexpr int bend = (16 * (b + 1) < K) ? 16 * (b + 1) : K;
+      constexpr int n = (bend - r0 < 4) ? bend - r0 : 4;
+      constexpr int NSL = NS - b;
+      double acc[n][NSL], src[n], mul[NSL];
+      sfor<0, n>([&](auto i_) {
+        src[i_.value] = A[G::off(b) + c];
+        sfor<0, NSL>([&](auto j_) { acc[i_.value][j_.value] = A[G::off(b + j_.value) + r0 + i_.value]; });
+      });
+      sfor<0, NSL>([&](auto j_) { mul[j_.value] = nL_[b + j_.value]; });
+      dpp_fmac<n, NSL, G::lane_of(r0), G::lane_of(r0 + (n > 1 ? 1 : 0)),
+               G::lane_of(r0 + (n > 2 ? 2 : 0)), G::lane_of(r0 + (n > 3 ? 3 : 0))>(acc, src, mul);
+      sfor<0, n>([&](auto i_) {
+        sfor<0, NSL>([&](auto j_) { A[G::off(b + j_.value) + r0 + i_.value] = acc[i_.value][j_.value]; });
+      });
+      if constexpr (r0 == c + 1) {
+        dvn = dpp_bcast<G::lane_of(c + 1)>(A[G::off((c + 1) / 16) + c + 1]);
+        rin = rcp_refined(dvn);
+      }
+    };
     // pivot of the next column: taken (and its reciprocal started) right
     // after the first update group of the current one, so that chain runs
     // under the remaining updates
-    double dv_next = bcast<G::lane_of(0)>(A[G::off(0) + 0]);
+    double dv_next = dpp_bcast<G::lane_of(0)>(A[G::off(0) + 0]);
     double ri_next = rcp_refined(dv_next);
     sfor<0, K>([&](auto c_) {
       constexpr int c = c_.value;
@@ -705,41 +769,22 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       const double ri = ri_next;
       if constexpr (c == K - 1) vself = dv;
       idg[sc] = (row_of(sc, l) == c) ? ri : idg[sc];
-      double Ls[NS];
+      // -Lt[row][c] = -A[row][c] / d_c for this lane's rows
+      double nL[NS];
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (16 * s + 15 > c) Ls[s] = A[G::off(s) + c] * ri;
+        if constexpr (16 * s + 15 > c) nL[s] = A[G::off(s) + c] * (-ri);
       });
-      // rows c+1.. in groups of four: the group's broadcasts are issued
-      // ahead of its updates, into distinct registers, so no update waits on
-      // the broadcast just before it
-      sfor<0, (K - c + 2) / 4>([&](auto g_) {
-        constexpr int r0 = c + 1 + 4 * g_.value;
-        double arc[4];
-        sfor<0, 4>([&](auto q_) {
-          constexpr int r = r0 + q_.value;
-          if constexpr (r < K) arc[q_.value] = bcast<G::lane_of(r)>(A[G::off(r / 16) + c]);
-        });
-        __builtin_amdgcn_sched_barrier(0);
-        sfor<0, 4>([&](auto q_) {
-          constexpr int r = r0 + q_.value;
-          if constexpr (r < K) {
-            sfor<0, NS>([&](auto s_) {
-              constexpr int s = s_.value;
-              if constexpr (16 * s + 15 >= r)
-                A[G::off(s) + r] = __builtin_fma(-Ls[s], arc[q_.value], A[G::off(s) + r]);
-            });
-          }
-        });
-        if constexpr (g_.value == 0 && c + 1 < K) {
-          dv_next = bcast<G::lane_of(c + 1)>(A[G::off((c + 1) / 16) + c + 1]);
-          ri_next = rcp_refined(dv_next);
-        }
-        __builtin_amdgcn_sched_barrier(0);
+      // rows r = c+1.. in groups of up to four rows of one 16-row block:
+      // A[row][r] += (A[r][c] broadcast from its owner) * (-Lt[row][c]) for
+      // the slots from that block on, the broadcast folded into the
+      // multiply-add
+      sfor<0, G::ngroups(c)>([&](auto g_) {
+        chol_group(c_, std::integral_constant<int, G::gstart(c, g_.value)>{}, nL, dv_next, ri_next);
       });
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (16 * s + 15 > c) A[G::off(s) + c] = Ls[s];
+        if constexpr (16 * s + 15 > c) A[G::off(s) + c] = nL[s];
       });
     });
     VEC_MARK("zero_upper");
@@ -761,49 +806,66 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int NV = std::extent<std::remove_reference_t<decltype(x)>, 0>::value;
       constexpr int sc = c / 16;
       constexpr int lc = G::lane_of(c);
-      // every right-hand side's broadcast first, then the updates
-      double xc[NV];
-      sfor<0, NV>([&](auto v_) { xc[v_.value] = bcast<lc>(x[v_.value][sc]); });
-      __builtin_amdgcn_sched_barrier(0);
-      sfor<0, NV>([&](auto v_) {
-        constexpr int v = v_.value;
-        sfor<0, NS>([&](auto s_) {
-          constexpr int s = s_.value;
-          if constexpr (16 * s + 15 > c) x[v][s] = __builtin_fma(-A[G::off(s) + c], xc[v], x[v][s]);
+      // x[v][row] += (x[v][c] broadcast from its owner) * (-Lt[row][c])
+      // (A holds -Lt) for the slots holding rows below c.  Slots go in
+      // decreasing order: the source x[v][sc] may share a register with the
+      // accumulator of slot sc, which must then be the last one updated.
+      constexpr int b = (c + 1) / 16;
+      if constexpr (b < NS) {
+        constexpr int NSL = NS - b;
+        double acc[NV][NSL], src[NV], mul[NSL];
+        sfor<0, NV>([&](auto v_) {
+          src[v_.value] = x[v_.value][sc];
+          sfor<0, NSL>([&](auto j_) { acc[v_.value][j_.value] = x[v_.value][NS - 1 - j_.value]; });
         });
-      });
-      __builtin_amdgcn_sched_barrier(0);
+        sfor<0, NSL>([&](auto j_) { mul[j_.value] = A[G::off(NS - 1 - j_.value) + c]; });
+        dpp_fmac<NV, NSL, lc, lc, lc, lc>(acc, src, mul);
+        sfor<0, NV>([&](auto v_) {
+          sfor<0, NSL>([&](auto j_) { x[v_.value][NS - 1 - j_.value] = acc[v_.value][j_.value]; });
+        });
+      }
     };
     auto fwd = [&](auto& x) { sfor<0, K>([&](auto c_) { fwd_step(c_, x); }); };
 
     // ---------------- ut = Lt^{-T} e_last via Lt in LDS ----------------
     VEC_MARK("backsolve");
     VEC_TMARK(6);
+    // Row r of Lt goes to Lp[r(r-1)/2 + c] for every column c < len(slot):
+    // entries at c >= r (zeros) run into the rows after r, at smaller
+    // columns.  Slots are stored in increasing row order and columns in
+    // decreasing order, so every such spill-over is overwritten later by the
+    // entry that belongs there; rows >= K write a sink.  No address
+    // arithmetic or select per entry.
     if constexpr (!kLik) {
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        const int r = row_of(s, l);
-        sfor<0, G::len(s)>([&](auto c_) {
-          constexpr int c = c_.value;
-          Lp[grp][(c < r && r < K) ? r * (r - 1) / 2 + c : LPN + l] = A[G::off(s) + c];
+        double* __restrict__ dst = &Lp[grp][lrow_base[s]];
+        sfor<0, G::len(s)>([&](auto cc_) {
+          constexpr int c = G::len(s) - 1 - cc_.value;
+          dst[c] = A[G::off(s) + c];
+          // the order matters across lanes, which the compiler cannot see:
+          // no reordering or pairing of these stores
+          asm volatile("" ::: "memory");
         });
       });
     }
     double uu[NS];
     sfor<0, NS>([&](auto s_) { uu[s_.value] = (row_of(s_.value, l) == K - 1) ? 1.0 : 0.0; });
     wave_lds_fence();
-    // Lt[r][row] for step r (0 where row >= r), read PF steps ahead
+    // Lt[r][row] for step r (0 where row >= r), read PF steps ahead: a
+    // static offset from the lane's column base (entries at row >= r lie
+    // inside Lp and are masked)
     auto lrow = [&](auto r_, double(&lv)[NS]) {
       constexpr int r = decltype(r_)::value;
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
+        const double* __restrict__ src = &Lp[grp][lcol_base[s]];
         if constexpr (r > 0 && 16 * s + 15 < r) {
           // every row of the slot lies below r
-          lv[s] = Lp[grp][r * (r - 1) / 2 + row_of(s, l)];
+          lv[s] = src[r * (r - 1) / 2];
         } else if constexpr (r > 0 && 16 * s < r) {
-          const int row = row_of(s, l);
-          const double v = Lp[grp][r * (r - 1) / 2 + (row < r ? row : r - 1)];
-          lv[s] = (row < r) ? v : 0.0;
+          const double v = src[r * (r - 1) / 2];
+          lv[s] = (row_of(s, l) < r) ? v : 0.0;
         } else {
           lv[s] = 0.0;
         }
@@ -820,11 +882,19 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       double lv[NS];
       sfor<0, NS>([&](auto s_) { lv[s_.value] = lvq[x % PF][s_.value]; });
       if constexpr (r - PF >= 0) lrow(std::integral_constant<int, r - PF>{}, lvq[x % PF]);
-      const double xr = bcast<lr>(xv[sr]);
-      sfor<0, NS>([&](auto s_) {
-        constexpr int s = s_.value;
-        if constexpr (16 * s < r) xv[s] = __builtin_fma(-lv[s], xr, xv[s]);
-      });
+      // xv[row] += (xv[r] broadcast from its owner) * (-Lt[r][row]) for the
+      // slots holding rows above r (Lp holds -Lt); the source may share a
+      // register with the accumulator of slot sr, the last one updated
+      if constexpr (r > 0) {
+        constexpr int NSL = (r - 1) / 16 + 1;
+        double acc[1][NSL], src[1] = {xv[sr]}, mul[NSL];
+        sfor<0, NSL>([&](auto j_) {
+          acc[0][j_.value] = xv[j_.value];
+          mul[j_.value] = lv[j_.value];
+        });
+        dpp_fmac<1, NSL, lr>(acc, src, mul);
+        sfor<0, NSL>([&](auto j_) { xv[j_.value] = acc[0][j_.value]; });
+      }
     };
     auto back_prefetch = [&](auto& lvq) {
       sfor<0, PF>([&](auto x_) { lrow(std::integral_constant<int, K - 1 - x_.value>{}, lvq[x_.value]); });
@@ -931,7 +1001,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
           // diagonal has h2 = 0 and padding rows exp(-h) = 0: both add 0)
           sfor<0, NS>([&](auto s_) {
             constexpr int s = s_.value;
-            double h2 = 0.0;
+            double h2 = kH2Floor;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
               const double dz = zrow[s][k] - zb[k];
@@ -950,7 +1020,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
             qq = __builtin_fma(qq, r, 0.5);
             qq = __builtin_fma(qq, r, 1.0);
             qq *= r;
-            const double sE = cf.sigma2 * ldexp(__builtin_fma(T, qq, T), in >> 6);
+            const double sE = ldexp(__builtin_fma(T, qq, T), in >> 6);
             const double sF = sE * __builtin_fma(cf.a1, hh, __builtin_fma(cf.a2, hi, cf.a0));
             Sv[s] = (NG == 1) ? sF * h2 * cf.ir[0] : sF;
           });
