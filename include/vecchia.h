@@ -113,11 +113,12 @@ int vec_nparms(const vec_problem* pb);
 int vec_nraw(const vec_problem* pb);
 int vec_nout(const vec_problem* pb);
 
-/* Largest m that every entry point accepts (40): the batched calls and the
- * loglik-only, adjoint, kriging-weights and prediction passes stop there.
- * vec_raw_sums, vec_block_sums, vecchia_loglik_grad_info and the Fisher
- * calls accept m <= 63 for every family; neighbourhoods of more than 41
- * observations (and VEC_FAMILY_ANISO) run on a kernel that gives each
+/* Largest m that every single-problem entry point accepts (60, the
+ * neighbour count of the paper's largest setting): the loglik-only, adjoint,
+ * kriging-weights and prediction passes stop there, and the batched calls at
+ * m = 40.  vec_raw_sums, vec_block_sums, vecchia_loglik_grad_info and the
+ * Fisher calls accept m <= 63 for every family; neighbourhoods of more than
+ * 61 observations (and VEC_FAMILY_ANISO) run on a kernel that gives each
  * neighbourhood a whole wave. */
 int vec_max_m(void);
 

@@ -32,6 +32,10 @@ VEC_DECLARE_K(11);
 VEC_DECLARE_K(21);
 VEC_DECLARE_K(31);
 VEC_DECLARE_K(41);
+#define VEC_DECLARE_SINGLE(K, PC, NG, MODE, B) extern template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE, B)
+VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 1);
+VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 2);
+VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 3);
 
 // kLaunch[K index][p - 1][space-time][mode]: single problem
 #define VEC_NG(K, PC, NG)                                                                   \
@@ -41,14 +45,14 @@ VEC_DECLARE_K(41);
 #define VEC_ROW(K) {VEC_PC(K, 1), VEC_PC(K, 2), VEC_PC(K, 3)}
 constexpr int kNumModes = 4;
 static const launch_fn kLaunch[kNumK][3][2][kNumModes] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31),
-                                                           VEC_ROW(41)};
+                                                           VEC_ROW(41), VEC_ROW(61)};
 // kLaunchBatch / kResidentBatch[K index][p - 1][space-time]: batched sums
 #define VEC_BPC(K, PC, F) {F<K, PC, 1, kModeSums, true>, F<K, PC, 2, kModeSums, true>}
 #define VEC_BROW(K, F) {VEC_BPC(K, 1, F), VEC_BPC(K, 2, F), VEC_BPC(K, 3, F)}
-static const launch_fn kLaunchBatch[kNumK][3][2] = {
+static const launch_fn kLaunchBatch[kNumBatchK][3][2] = {
     VEC_BROW(11, launch_sums), VEC_BROW(21, launch_sums), VEC_BROW(31, launch_sums),
     VEC_BROW(41, launch_sums)};
-static const resident_fn kResidentBatch[kNumK][3][2] = {
+static const resident_fn kResidentBatch[kNumBatchK][3][2] = {
     VEC_BROW(11, resident_sums), VEC_BROW(21, resident_sums), VEC_BROW(31, resident_sums),
     VEC_BROW(41, resident_sums)};
 
@@ -603,7 +607,7 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
 // batches of datasets
 // ----------------------------------------------------------------------------
 
-static_assert(VEC_NUM_CLASSES == kNumK, "one size class per kernel size");
+static_assert(VEC_NUM_CLASSES == kNumBatchK, "one size class per batched kernel size");
 constexpr int kDefaultTile = 32;
 constexpr int kMaxTile = 1 << 20;
 constexpr int kMaxSets = 65535;
@@ -619,8 +623,8 @@ static PlanLayout plan_layout(int32_t nsets) {
   PlanLayout L;
   L.sets = 0;
   L.prefix = align256((size_t)nsets * kSetFields * sizeof(int64_t));
-  L.ids = L.prefix + align256((size_t)kNumK * (nsets + 1) * sizeof(int64_t));
-  L.bytes = L.ids + align256((size_t)kNumK * nsets * sizeof(int32_t));
+  L.ids = L.prefix + align256((size_t)kNumBatchK * (nsets + 1) * sizeof(int64_t));
+  L.bytes = L.ids + align256((size_t)kNumBatchK * nsets * sizeof(int32_t));
   return L;
 }
 
@@ -658,11 +662,11 @@ static int enqueue_batch_sums(const vec_batch* bt, const Dims& dm, const vec_bat
   double* partials = static_cast<double*>(ws);
   unsigned int* counters = reinterpret_cast<unsigned int*>(
       static_cast<char*>(ws) + align256((size_t)plan->rows * dm.nraw * sizeof(double)));
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, counters, kNumK, 0u);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, counters, kNumBatchK, 0u);
   const int pc = dm.p - 1, ng = (bt->family == VEC_FAMILY_SPACETIME) ? 1 : 0;
   int64_t row0 = 0;
   // largest neighbourhoods first
-  for (int c = kNumK - 1; c >= 0; --c) {
+  for (int c = kNumBatchK - 1; c >= 0; --c) {
     if (plan->ntiles[c] == 0) continue;
     SumsArgs args = {};
     args.d = bt->d;
@@ -1151,7 +1155,7 @@ int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_
   if (plan_dev_bytes < L.bytes) return VEC_EWORKSPACE;
   vec_batch_plan pl = {};
   pl.nsets = ns;
-  for (int c = 0; c < kNumK; ++c) {
+  for (int c = 0; c < kNumBatchK; ++c) {
     const int t = sched ? sched->tile[c] : 0;
     const int b = sched ? sched->blocks_per_cu[c] : 0;
     if (t < 0 || t > kMaxTile || b < 0 || b > 64) return VEC_EINVAL;
@@ -1163,7 +1167,7 @@ int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_
   for (int32_t b = 0; b < ns; ++b) {
     const vec_dataset& s = sets[b];
     if (s.reserved != 0 || s.n < 1 || s.n >= (int64_t)INT32_MAX) return VEC_EINVAL;
-    if (s.m < 0 || s.m > kKs[kNumK - 1] - 1 || nu_code(s.smoothness) < 0) return VEC_EINVAL;
+    if (s.m < 0 || s.m > kKs[kNumBatchK - 1] - 1 || nu_code(s.smoothness) < 0) return VEC_EINVAL;
     if (s.obs_offset < 0 || s.obs_offset > bt->n_total - s.n) return VEC_EINVAL;
     const int64_t nn_entries = s.n * (int64_t)(s.m + 1);
     if (s.nn_offset < 0 || s.nn_offset > bt->nn_total - nn_entries) return VEC_EINVAL;
@@ -1172,10 +1176,10 @@ int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_
     cls[b] = c;
   }
   std::vector<int64_t> hsets((size_t)ns * kSetFields);
-  std::vector<int64_t> hprefix((size_t)kNumK * (ns + 1), 0);
-  std::vector<int32_t> hids((size_t)kNumK * ns, 0);
+  std::vector<int64_t> hprefix((size_t)kNumBatchK * (ns + 1), 0);
+  std::vector<int32_t> hids((size_t)kNumBatchK * ns, 0);
   int64_t row = 0;
-  for (int c = 0; c < kNumK; ++c) {
+  for (int c = 0; c < kNumBatchK; ++c) {
     int32_t cnt = 0;
     int64_t tiles = 0;
     int64_t* prefix = hprefix.data() + (size_t)c * (ns + 1);
@@ -1212,7 +1216,7 @@ int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_
       ncu = v;
   }
   const int pc = dm.p - 1, ng = (bt->family == VEC_FAMILY_SPACETIME) ? 1 : 0;
-  for (int c = 0; c < kNumK; ++c) {
+  for (int c = 0; c < kNumBatchK; ++c) {
     int per_cu = pl.sched.blocks_per_cu[c];
     if (per_cu == 0) per_cu = kResidentBatch[c][pc][ng]();
     if (per_cu <= 0) per_cu = 1;

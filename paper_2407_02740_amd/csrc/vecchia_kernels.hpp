@@ -304,21 +304,30 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
 
   // per-row record: scaled coordinates z[0..3] (space-time: time in z[3])
   // and u
-  constexpr int RZ = 0, RU = 4;
+  // and u, and the row's inverse pivot 1/d_r (0 for rows >= K)
+  constexpr int RZ = 0, RU = 4, RI = 5;
   constexpr int RS = 6;  // row stride, 16-byte aligned
   __shared__ double rec[kGroupsPerBlock][KP][RS];
   // rows 0..K-1 packed at r(r-1)/2 (stores of a row run past its diagonal
   // into later rows, see the store below), then a sink for rows >= K
   constexpr int LPS = LPN + 1 + K;
-  __shared__ double Lp[kGroupsPerBlock][kLik ? 1 : LPS];
+  // Above K = 41 a copy of Lt would take the LDS of two more workgroups per
+  // CU: the back substitutions then run row by row on the factor in
+  // registers, one 16-lane sum per row.
+  constexpr bool kRowBack = K > 41;
+  __shared__ double Lp[kGroupsPerBlock][(kLik || kRowBack) ? 1 : LPS];
   __shared__ double acc[kGroupsPerBlock][NRAW];
   // running product of conditional variances (mantissa, exponent)
   __shared__ double vprod[kGroupsPerBlock][2];
   // per strictly-lower pair (r, c), index r(r-1)/2 + c: sigma2 (-f'(h)/h),
   // from which every range derivative of the pair follows (last slot: sink
   // for diagonal entries)
-  constexpr int NPAIR = KP * (KP - 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][kStoreF ? NPAIR + 2 : 2];  // + write sink, + zero
+  // per pair (r, c), c <= r, at r(r+1)/2 + c: sigma2 (-f'(h)/h), from which
+  // every range derivative of the pair follows (on the diagonal the
+  // squared coordinate differences that multiply it are 0)
+  // (+ a write sink for the upper-triangle steps of an unpaired last slot)
+  constexpr int NQ = KP * (KP + 1) / 2;
+  __shared__ double sfv[kGroupsPerBlock][kStoreF ? NQ + (NS & 1) : 2];
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -378,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   };
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
-  if (kStoreF && threadIdx.x < kGroupsPerBlock) sfv[threadIdx.x][NPAIR + 1] = 0.0;
+  for (int e = threadIdx.x; e < kGroupsPerBlock * KP; e += kThreads) rec[e / KP][e % KP][RI] = 0.0;
   static_assert(kThreads == 64, "one table entry per thread");
   __syncthreads();
   if (threadIdx.x < kGroupsPerBlock) {
@@ -602,13 +611,16 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
       const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
       if constexpr (kStoreF) {
-        sfv[grp][idx0] = (NG == 1) ? sF0 * h20 * cf.ir[0] : sF0;
-        sfv[grp][idx1] = (NG == 1) ? sF1 * h21 * cf.ir[0] : sF1;
+        // isotropic: the finished dSigma/drho entry, sF h^2 / rho (h^2 without
+        // the floor, so that it is exactly 0 on the diagonal and at
+        // coincident locations)
+        sfv[grp][idx0] = (NG == 1) ? sF0 * (h20 - kH2Floor) * cf.ir[0] : sF0;
+        sfv[grp][idx1] = (NG == 1) ? sF1 * (h21 - kH2Floor) * cf.ir[0] : sF1;
       }
       v0 = sE0 * __builtin_fma(hh0, __builtin_fma(hh0, cf.c2, cf.c1), 1.0);
       v1 = sE1 * __builtin_fma(hh1, __builtin_fma(hh1, cf.c2, cf.c1), 1.0);
     };
-    auto pidx = [](int r, int c) { return r * (r - 1) / 2 + c; };
+    auto pidx = [](int r, int c) { return r * (r + 1) / 2 + c; };
 
     VEC_MARK("phase1");
     VEC_TMARK(2);
@@ -656,11 +668,14 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     sfor<0, NS / 2>([&](auto t_) {
       constexpr int s0 = 2 * t_.value;
       constexpr int s1 = s0 + 1;
-      auto locate = [&](auto u_, int& r, int& c, double(&zr)[4], double(&zc)[4]) {
+      const int ra = 16 * s0 + l, rb = 16 * s1 + 15 - l;
+      const int qa = ra * (ra + 1) / 2, qb = rb * (rb + 1) / 2;
+      auto locate = [&](auto u_, int& r, int& c, int& q, double(&zr)[4], double(&zc)[4]) {
         constexpr int u = decltype(u_)::value;
         const bool first = (u <= l);
         c = first ? 16 * s0 + u : 16 * s1 + 16 - u;
-        r = first ? 16 * s0 + l : 16 * s1 + 15 - l;
+        r = first ? ra : rb;
+        q = first ? qa + (16 * s0 + u) : qb + (16 * s1 + 16 - u);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           zr[k] = rec[grp][r][RZ + k];
@@ -673,13 +688,13 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         if constexpr (u <= 15) A[G::off(s0) + 16 * s0 + u] = v;
         if constexpr (u >= 1 && 16 * s1 + 16 - u < K) A[G::off(s1) + 16 * s1 + 16 - u] = v;
       };
-      int rn[2], cn[2];
+      int rn[2], cn[2], qn[2];
       double zrn[2][4], zcn[2][4];
-      locate(std::integral_constant<int, 0>{}, rn[0], cn[0], zrn[0], zcn[0]);
-      locate(std::integral_constant<int, 1>{}, rn[1], cn[1], zrn[1], zcn[1]);
+      locate(std::integral_constant<int, 0>{}, rn[0], cn[0], qn[0], zrn[0], zcn[0]);
+      locate(std::integral_constant<int, 1>{}, rn[1], cn[1], qn[1], zrn[1], zcn[1]);
       sfor<0, 9>([&](auto w_) {
         constexpr int u = 2 * w_.value;          // steps u and u + 1 (17 steps)
-        int r[2] = {rn[0], rn[1]}, c[2] = {cn[0], cn[1]};
+        int r[2] = {rn[0], rn[1]}, c[2] = {cn[0], cn[1]}, q[2] = {qn[0], qn[1]};
         double zr[2][4], zc[2][4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -688,18 +703,16 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
           zr[1][k] = zrn[1][k];
           zc[1][k] = zcn[1][k];
         }
-        if constexpr (u + 2 < 17) locate(std::integral_constant<int, u + 2>{}, rn[0], cn[0], zrn[0], zcn[0]);
-        if constexpr (u + 3 < 17) locate(std::integral_constant<int, u + 3>{}, rn[1], cn[1], zrn[1], zcn[1]);
+        if constexpr (u + 2 < 17) locate(std::integral_constant<int, u + 2>{}, rn[0], cn[0], qn[0], zrn[0], zcn[0]);
+        if constexpr (u + 3 < 17) locate(std::integral_constant<int, u + 3>{}, rn[1], cn[1], qn[1], zrn[1], zcn[1]);
         double off0, off1;
         if constexpr (u + 1 < 17) {
-          pair_eval2(zr[0], zc[0], (c[0] == r[0]) ? NPAIR : pidx(r[0], c[0]), zr[1], zc[1],
-                     (c[1] == r[1]) ? NPAIR : pidx(r[1], c[1]), off0, off1);
+          pair_eval2(zr[0], zc[0], q[0], zr[1], zc[1], q[1], off0, off1);
           store(std::integral_constant<int, u>{}, r[0], c[0], off0);
           store(std::integral_constant<int, u + 1>{}, r[1], c[1], off1);
         } else {
           // last (odd) step: the second slot of the evaluation repeats it
-          pair_eval2(zr[0], zc[0], (c[0] == r[0]) ? NPAIR : pidx(r[0], c[0]), zr[0], zc[0],
-                     NPAIR, off0, off1);
+          pair_eval2(zr[0], zc[0], q[0], zr[0], zc[0], q[0], off0, off1);
           store(std::integral_constant<int, u>{}, r[0], c[0], off0);
         }
       });
@@ -714,7 +727,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
         double off, dup;
-        pair_eval2(zo[s], zc, (c < r) ? pidx(r, c) : NPAIR, zo[s], zc, NPAIR, off, dup);
+        // steps past the lane's row (upper triangle) write the sink
+        pair_eval2(zo[s], zc, (c <= r) ? pidx(r, c) : NQ, zo[s], zc, NQ, off, dup);
         A[G::off(s) + c] = (c == r) ? cf.diag : off;
       });
     }
@@ -727,7 +741,6 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // broadcast the pivot d_c and each unscaled entry A[r][c]; rows update
     // with Lt[row][c] = A[row][c] / d_c.  The owner of row r keeps 1/d_r.
     double idg[NS];
-    sfor<0, NS>([&](auto s_) { idg[s_.value] = 0.0; });
     bool notpd = false;
     double vself = 1.0;
     // One group of column c's updates: rows r0 .. r0+n-1 of block b, then
@@ -768,7 +781,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       notpd |= !(dv > 0.0);
       const double ri = ri_next;
       if constexpr (c == K - 1) vself = dv;
-      idg[sc] = (row_of(sc, l) == c) ? ri : idg[sc];
+      rec[grp][c][RI] = ri;  // the same value from every lane
       // -Lt[row][c] = -A[row][c] / d_c for this lane's rows
       double nL[NS];
       sfor<0, NS>([&](auto s_) {
@@ -798,6 +811,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         A[G::off(s) + c] = (c >= r) ? 0.0 : A[G::off(s) + c];
       });
     });
+    // 1/d of this lane's rows
+    sfor<0, NS>([&](auto s_) { idg[s_.value] = rec[grp][row_of(s_.value, l)][RI]; });
 
     // forward substitution x <- Lt^{-1} x (unit lower) for NV right-hand
     // sides, one column step at a time
@@ -836,7 +851,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // decreasing order, so every such spill-over is overwritten later by the
     // entry that belongs there; rows >= K write a sink.  No address
     // arithmetic or select per entry.
-    if constexpr (!kLik) {
+    if constexpr (!kLik && !kRowBack) {
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
         double* __restrict__ dst = &Lp[grp][lrow_base[s]];
@@ -897,7 +912,23 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       }
     };
     auto back_prefetch = [&](auto& lvq) {
-      sfor<0, PF>([&](auto x_) { lrow(std::integral_constant<int, K - 1 - x_.value>{}, lvq[x_.value]); });
+      if constexpr (!kRowBack)
+        sfor<0, PF>([&](auto x_) { lrow(std::integral_constant<int, K - 1 - x_.value>{}, lvq[x_.value]); });
+    };
+    // Row-oriented step x of the same substitution (no copy of Lt): row
+    // a = K - 2 - x gets xv[a] += sum_{r > a} (-Lt[r][a]) xv[r], the sum over
+    // the lanes' rows from the factor in registers (upper entries are 0, so
+    // no masks), then one 16-lane sum; the owner of row a adds it.
+    auto back_step_rows = [&](auto x_, double(&xv)[NS]) {
+      constexpr int a = K - 2 - decltype(x_)::value;
+      if constexpr (a >= 0) {
+        constexpr int b = (a + 1) / 16;  // slots holding rows > a
+        double t = 0.0;
+        sfor<b, NS>([&](auto s_) { t = __builtin_fma(A[G::off(s_.value) + a], xv[s_.value], t); });
+        t = row_allreduce(t);
+        constexpr int sa = a / 16;
+        xv[sa] = (l == G::lane_of(a)) ? xv[sa] + t : xv[sa];
+      }
     };
     if constexpr (kLik) {
       fwd(rhs);
@@ -907,7 +938,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       // The back substitution (latency bound: one broadcast per step) runs
       // interleaved with the independent forward substitution of y and X.
       sfor<0, K>([&](auto x_) {
-        back_step(x_, lvq, uu);
+        if constexpr (kRowBack)
+          back_step_rows(x_, uu);
+        else
+          back_step(x_, lvq, uu);
         fwd_step(x_, rhs);
       });
       // rhs = Lt^{-1} (y, X);  uu = Lt^{-T} e_last (u = uu / sqrt(d_last))
@@ -951,7 +985,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int a = row_of(s, l);
-      base_a[s] = a * (a - 1) / 2;
+      base_a[s] = a * (a + 1) / 2;
       if constexpr (NG == 2 || kRecomp) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) zrow[s][k] = rec[grp][a][RZ + k];
@@ -961,7 +995,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     });
     auto col_load = [&](auto b_, double& ub, double(&zb)[4], double(&Sv)[NS]) {
       constexpr int b = decltype(b_)::value;
-      constexpr int CB = b * (b - 1) / 2;
+      constexpr int CB = b * (b + 1) / 2;
       ub = rec[grp][b][RU];
       if constexpr (NG == 2 || kRecomp) {
 #pragma unroll
@@ -976,11 +1010,86 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         else if constexpr (b >= 16 * (s + 1))
           idx = a + CB;
         else
-          idx = (b < a) ? base_a[s] + b : ((b > a) ? a + CB : NPAIR + 1);
+          idx = (b <= a) ? base_a[s] + b : a + CB;
         Sv[s] = sfv[grp][idx];
       });
     };
-    {
+    // pair factor of (row of slot s, column b) again, as in phase 1 (the
+    // diagonal has h2 = 0 and padding rows exp(-h) = 0: both add 0)
+    auto recompute = [&](const double(&zb)[4], double(&Sv)[NS]) {
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        double h2 = kH2Floor;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double dz = zrow[s][k] - zb[k];
+          h2 = __builtin_fma(dz, dz, h2);
+        }
+        double hh, hi;
+        dist_from_sq(h2, hh, hi);
+        const double x = fmax(-hh, -800.0);
+        const double nn = rint(x * kInvLn2x64);
+        const int in = (int)nn;
+        const double T = exptab[in & 63];
+        double r = __builtin_fma(-nn, kLn2d64Hi, x);
+        r = __builtin_fma(-nn, kLn2d64Lo, r);
+        double qq = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+        qq = __builtin_fma(qq, r, 1.0 / 6.0);
+        qq = __builtin_fma(qq, r, 0.5);
+        qq = __builtin_fma(qq, r, 1.0);
+        qq *= r;
+        const double sE = ldexp(__builtin_fma(T, qq, T), in >> 6);
+        const double sF = sE * __builtin_fma(cf.a1, hh, __builtin_fma(cf.a2, hi, cf.a0));
+        Sv[s] = (NG == 1) ? sF * (h2 - kH2Floor) * cf.ir[0] : sF;
+      });
+    };
+    // g_rho[row] += dSigma/drho (row, b) u_b for this lane's rows
+    auto accumulate_col = [&](double ub, const double(&zb)[4], const double(&Sv)[NS]) {
+      sfor<0, NS>([&](auto s_) {
+        constexpr int s = s_.value;
+        if constexpr (NG == 1) {
+          // stored directly as dSigma/drho for the isotropic family
+          gr[0][s] = __builtin_fma(Sv[s], ub, gr[0][s]);
+        } else {
+          const double d0 = zrow[s][0] - zb[0];
+          double h2s = d0 * d0;
+#pragma unroll
+          for (int k = 1; k < 3; ++k) {
+            const double dz = zrow[s][k] - zb[k];
+            h2s = __builtin_fma(dz, dz, h2s);
+          }
+          const double dt = zrow[s][3] - zb[3];
+          const double Su = Sv[s] * ub;
+          gr[0][s] = __builtin_fma(Su, h2s, gr[0][s]);
+          gr[1][s] = __builtin_fma(Su, dt * dt, gr[1][s]);
+        }
+      });
+    };
+    if constexpr (kRecomp && K > 41) {
+      // Large neighbourhoods: a runtime loop over the columns keeps the
+      // code small (the pair factors come from the coordinates, nothing is
+      // indexed by register); the adjoint's back substitution runs first.
+      if constexpr (kAdj) {
+        sfor<0, NS>([&](auto s_) { al[s_.value] = rhs[0][s_.value] * idg[s_.value]; });
+        sfor<0, K>([&](auto x_) { back_step_rows(x_, al); });
+      }
+      double ubn = rec[grp][0][RU], zbn[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) zbn[k] = rec[grp][0][RZ + k];
+      for (int b = 0; b < K; ++b) {
+        const double ub = ubn;
+        double zb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zb[k] = zbn[k];
+        const int bn = (b + 1 < K) ? b + 1 : b;
+        ubn = rec[grp][bn][RU];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zbn[k] = rec[grp][bn][RZ + k];
+        double Sv[NS];
+        recompute(zb, Sv);
+        accumulate_col(ub, zb, Sv);
+      }
+    } else {
       double alq[PF][NS];
       if constexpr (kAdj) {
         sfor<0, NS>([&](auto s_) { al[s_.value] = rhs[0][s_.value] * idg[s_.value]; });
@@ -990,59 +1099,19 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       col_load(std::integral_constant<int, 0>{}, ubn, zbn, Svn);
       sfor<0, K>([&](auto b_) {
         constexpr int b = b_.value;
-        if constexpr (kAdj) back_step(b_, alq, al);
+        if constexpr (kAdj) {
+          if constexpr (kRowBack)
+            back_step_rows(b_, al);
+          else
+            back_step(b_, alq, al);
+        }
         double ub = ubn, zb[4], Sv[NS];
 #pragma unroll
         for (int k = 0; k < 4; ++k) zb[k] = zbn[k];
         sfor<0, NS>([&](auto s_) { Sv[s_.value] = Svn[s_.value]; });
         if constexpr (b + 1 < K) col_load(std::integral_constant<int, b + 1>{}, ubn, zbn, Svn);
-        if constexpr (kRecomp) {
-          // sigma2 (-f'(h)/h) of the pair (a, b) again, as in phase 1 (the
-          // diagonal has h2 = 0 and padding rows exp(-h) = 0: both add 0)
-          sfor<0, NS>([&](auto s_) {
-            constexpr int s = s_.value;
-            double h2 = kH2Floor;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const double dz = zrow[s][k] - zb[k];
-              h2 = __builtin_fma(dz, dz, h2);
-            }
-            double hh, hi;
-            dist_from_sq(h2, hh, hi);
-            const double x = fmax(-hh, -800.0);
-            const double nn = rint(x * kInvLn2x64);
-            const int in = (int)nn;
-            const double T = exptab[in & 63];
-            double r = __builtin_fma(-nn, kLn2d64Hi, x);
-            r = __builtin_fma(-nn, kLn2d64Lo, r);
-            double qq = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
-            qq = __builtin_fma(qq, r, 1.0 / 6.0);
-            qq = __builtin_fma(qq, r, 0.5);
-            qq = __builtin_fma(qq, r, 1.0);
-            qq *= r;
-            const double sE = ldexp(__builtin_fma(T, qq, T), in >> 6);
-            const double sF = sE * __builtin_fma(cf.a1, hh, __builtin_fma(cf.a2, hi, cf.a0));
-            Sv[s] = (NG == 1) ? sF * h2 * cf.ir[0] : sF;
-          });
-        }
-        sfor<0, NS>([&](auto s_) {
-          constexpr int s = s_.value;
-          if constexpr (NG == 1) {
-            // stored directly as dSigma/drho for the isotropic family
-            gr[0][s] = __builtin_fma(Sv[s], ub, gr[0][s]);
-          } else {
-            double h2s = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              const double dz = zrow[s][k] - zb[k];
-              h2s = __builtin_fma(dz, dz, h2s);
-            }
-            const double dt = zrow[s][3] - zb[3];
-            const double Su = Sv[s] * ub;
-            gr[0][s] = __builtin_fma(Su, h2s, gr[0][s]);
-            gr[1][s] = __builtin_fma(Su, dt * dt, gr[1][s]);
-          }
-        });
+        if constexpr (kRecomp) recompute(zb, Sv);
+        accumulate_col(ub, zb, Sv);
       });
     }
     if constexpr (NG == 2) {
@@ -1300,9 +1369,21 @@ using resident_fn = int (*)();
 #define VECCHIA_FOR_MODES(X, K, PC) \
   VECCHIA_FOR_NG(X, K, PC, 1);      \
   VECCHIA_FOR_NG(X, K, PC, 2)
+// single-problem modes only (sizes without a batched class)
+#define VECCHIA_FOR_SINGLE(X, K, PC) \
+  X(K, PC, 1, 0, false);             \
+  X(K, PC, 1, 1, false);             \
+  X(K, PC, 1, 2, false);             \
+  X(K, PC, 1, 3, false);             \
+  X(K, PC, 2, 0, false);             \
+  X(K, PC, 2, 1, false);             \
+  X(K, PC, 2, 2, false);             \
+  X(K, PC, 2, 3, false)
 
-// Instantiated K values (K >= m + 1 is padded with identity rows).
-constexpr int kNumK = 4;
-constexpr int kKs[kNumK] = {11, 21, 31, 41};
+// Instantiated K values (K >= m + 1 is padded with identity rows); the
+// batched launches use the first kNumBatchK of them.
+constexpr int kNumK = 5;
+constexpr int kKs[kNumK] = {11, 21, 31, 41, 61};
+constexpr int kNumBatchK = 4;
 
 }  // namespace vecchia

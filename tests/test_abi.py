@@ -40,7 +40,7 @@ def test_problem_sizes_and_validation_on_host():
     assert L.vec_nout(ctypes.byref(pb)) == 1 + 4 + 16 + 1 + 1
     pb2 = V.Problem(n=1000, m=30, d=2, p=3, family=V.FAMILY_ISO, smoothness=1.5, nspace=0)
     assert L.vec_nraw(ctypes.byref(pb2)) == 65
-    assert L.vec_max_m() == 40
+    assert L.vec_max_m() == 60
     # beyond the fused kernel's sizes the sums still accept m <= 63
     pb3 = V.Problem(n=1000, m=60, d=2, p=1, family=V.FAMILY_ISO, smoothness=0.5, nspace=0)
     assert L.vec_nparms(ctypes.byref(pb3)) == 3
