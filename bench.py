@@ -164,6 +164,9 @@ def main():
                     choices=["satellite_spacetime", "batched_uneven", "surrogate_plane",
                              "sweep", "predict", "neighbours", "attributes_18d",
                              "grouped_plane", "pipeline"])
+    ap.add_argument("--sweep-sizes", default="32768,131072,524288,2097152,4194304",
+                    help="sweep workload: comma-separated n values")
+    ap.add_argument("--sweep-ms", default="10,30,40,60", help="sweep workload: comma-separated m")
     ap.add_argument("--train-neighbourhoods", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=2)
     args = ap.parse_args()
@@ -518,14 +521,17 @@ def bench_sweep(args):
     torch.cuda.set_device(0)
     rows = []
     cp = np.array((1.0, 0.05, 0.05))
-    for n in (1 << 15, 1 << 17, 1 << 19, 1 << 21, 1 << 22):
+    sizes = [int(v) for v in args.sweep_sizes.split(",")]
+    ms = [int(v) for v in args.sweep_ms.split(",")]
+    assert max(ms) <= 60, "the sweep's neighbour arrays hold 60 neighbours"
+    for n in sizes:
         rng = np.random.default_rng(7)
         locs = rng.random((n, 2))
         locs = np.ascontiguousarray(locs[S.maxmin_approx(locs, 7)])
         NN60 = V.ordered_nn(torch.as_tensor(locs, device="cuda"), 60).cpu().numpy()
         y = S.rff_field(locs / cp[1], 1.5, 128, rng) + np.sqrt(cp[2]) * rng.standard_normal(n)
         X = np.ones((n, 1))
-        for m in (10, 30, 40, 60):
+        for m in ms:
             NN = np.ascontiguousarray(NN60[:, :m + 1])
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
@@ -551,12 +557,14 @@ def bench_sweep(args):
                 out = ev2.loglik_grad_info(ev2.covparms(cp), check=False).cpu()
             e2e = (time.perf_counter() - t0) * 1e3
             del ev2
+            F = algorithmic_flops(m + 1, 2, 1, 1)
             row = dict(n=n, m=m, kernel_ms=kern, nbhd_per_s=n / (kern * 1e-3), end_to_end_ms=e2e,
                        end_to_end_nbhd_per_s=n / (e2e * 1e-3), loglik=float(out[0]),
-                       kernel="fused" if m + 1 <= 61 else "wave")
+                       kernel="fused" if m + 1 <= 61 else "wave", flop_per_neighbourhood=F,
+                       fp64_frac=F * n / (kern * 1e-3) / 78.6e12)
             rows.append(row)
-            log(f"n={n} m={m}: {kern:.3f} ms ({row['nbhd_per_s']:.3e} nbhd/s), end to end "
-                f"{e2e:.1f} ms")
+            log(f"n={n} m={m}: {kern:.3f} ms ({row['nbhd_per_s']:.3e} nbhd/s, "
+                f"{100 * row['fp64_frac']:.1f} % of FP64 peak), end to end {e2e:.1f} ms")
     line = {"metric": "neighbourhoods/s (loglik+grad+Fisher) over n and m, 2-D Matern 3/2",
             "value": None, "unit": "neighbourhoods/s", "n_gpus": 1, "steps": args.steps,
             "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",

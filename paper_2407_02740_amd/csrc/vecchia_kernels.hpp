@@ -289,9 +289,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   constexpr bool kLik = MODE == kModeLoglik;
   constexpr bool kWts = MODE == kModeWeights;
   constexpr bool kDeriv = kFull || kAdj;  // derivative work: pair factors and phase 2
-  // Above K = 31 the stored pair factors would take the LDS of two more
+  // Above K = 41 the stored pair factors would take the LDS of two more
   // workgroups per CU: phase 2 recomputes them from the coordinates instead.
-  constexpr bool kRecomp = kDeriv && K > 31;
+  constexpr bool kRecomp = kDeriv && K > 41;
   constexpr bool kStoreF = kDeriv && !kRecomp;
   constexpr int NRAW = nraw_mode(MODE, PC, P);
   constexpr int RC = kAdj ? 1 : 1 + PC;  // right-hand sides of the forward substitution
@@ -302,32 +302,33 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   constexpr int NGR = NR * (NR + 1) / 2;
   constexpr int NPART = NR + NR * PC + NGR;
 
-  // per-row record: scaled coordinates z[0..3] (space-time: time in z[3])
-  // and u
-  // and u, and the row's inverse pivot 1/d_r (0 for rows >= K)
+  // per-row record: scaled coordinates z[0..3] (space-time: time in z[3]),
+  // u, and the row's inverse pivot 1/d_r (0 for rows >= K).  Rows that are
+  // never read as a partner -- the spare rows of an unpaired last slot --
+  // share one sink row at RROWS.
   constexpr int RZ = 0, RU = 4, RI = 5;
   constexpr int RS = 6;  // row stride, 16-byte aligned
-  __shared__ double rec[kGroupsPerBlock][KP][RS];
+  constexpr int RROWS = (K > 16 * (NS - (NS & 1))) ? K : 16 * (NS - (NS & 1));
+  constexpr int RREC = RROWS + (NS & 1);  // + the sink row (odd NS only)
+  __shared__ double rec[kGroupsPerBlock][RREC][RS];
   // rows 0..K-1 packed at r(r-1)/2 (stores of a row run past its diagonal
   // into later rows, see the store below), then a sink for rows >= K
   constexpr int LPS = LPN + 1 + K;
-  // Above K = 41 a copy of Lt would take the LDS of two more workgroups per
-  // CU: the back substitutions then run row by row on the factor in
-  // registers, one 16-lane sum per row.
-  constexpr bool kRowBack = K > 41;
+  // Above K = 31 a copy of Lt would take the LDS of another workgroup per
+  // CU (or leave no room for the pair factors): the back substitutions then
+  // run row by row on the factor in registers, one 16-lane sum per row.
+  constexpr bool kRowBack = K > 31;
   __shared__ double Lp[kGroupsPerBlock][(kLik || kRowBack) ? 1 : LPS];
   __shared__ double acc[kGroupsPerBlock][NRAW];
   // running product of conditional variances (mantissa, exponent)
   __shared__ double vprod[kGroupsPerBlock][2];
-  // per strictly-lower pair (r, c), index r(r-1)/2 + c: sigma2 (-f'(h)/h),
-  // from which every range derivative of the pair follows (last slot: sink
-  // for diagonal entries)
-  // per pair (r, c), c <= r, at r(r+1)/2 + c: sigma2 (-f'(h)/h), from which
-  // every range derivative of the pair follows (on the diagonal the
-  // squared coordinate differences that multiply it are 0)
-  // (+ a write sink for the upper-triangle steps of an unpaired last slot)
-  constexpr int NQ = KP * (KP + 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][kStoreF ? NQ + (NS & 1) : 2];
+  // per pair (r, c), c <= r < K, at r(r+1)/2 + c: sigma2 (-f'(h)/h), from
+  // which every range derivative of the pair follows (on the diagonal the
+  // squared coordinate differences that multiply it are 0); then a sink of
+  // KP entries for the rows >= K and for the upper-triangle steps of an
+  // unpaired last slot
+  constexpr int NQ = K * (K + 1) / 2;
+  __shared__ double sfv[kGroupsPerBlock][kStoreF ? NQ + KP : 2];
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -335,10 +336,15 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // Lp offsets of this lane's rows: where its row r starts (the sink for
   // rows >= K), and its column r in the rows below
   int lrow_base[NS], lcol_base[NS];
+  // and the start of its pair factors (the sink for rows >= K), and its row
+  // record (the sink row for rows >= RROWS)
+  int qrow_base[NS], rrow[NS];
   sfor<0, NS>([&](auto s_) {
     const int r = row_of(s_.value, lane);
     lrow_base[s_.value] = (r < K) ? r * (r - 1) / 2 : LPN + 1;
     lcol_base[s_.value] = r;
+    qrow_base[s_.value] = (r < K) ? r * (r + 1) / 2 : NQ;
+    rrow[s_.value] = (r < RROWS) ? r : RROWS;
   });
 
   // the problem of the current tile (BATCH: one dataset's slice)
@@ -387,7 +393,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   };
 
   for (int e = threadIdx.x; e < kGroupsPerBlock * NRAW; e += kThreads) (&acc[0][0])[e] = 0.0;
-  for (int e = threadIdx.x; e < kGroupsPerBlock * KP; e += kThreads) rec[e / KP][e % KP][RI] = 0.0;
+  for (int e = threadIdx.x; e < kGroupsPerBlock * RREC; e += kThreads)
+    rec[e / RREC][e % RREC][RI] = 0.0;
   static_assert(kThreads == 64, "one table entry per thread");
   __syncthreads();
   if (threadIdx.x < kGroupsPerBlock) {
@@ -552,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         zo[s][k] = has ? zc[k] : ((k == 0) ? kFar * (double)(1 + r) : 0.0);
-        rec[grp][r][RZ + k] = zo[s][k];
+        rec[grp][rrow[s]][RZ + k] = zo[s][k];
       }
       if constexpr (kAdj) {
         // residual at the given beta
@@ -657,7 +664,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
             }
           }
           const int r = row_of(s, l);
-          pair_eval2(zo[s], zc[0], pidx(r, c), zo[s], zc[1], pidx(r, c + 1), A[G::off(s) + c],
+          pair_eval2(zo[s], zc[0], qrow_base[s] + c, zo[s], zc[1], qrow_base[s] + c + 1, A[G::off(s) + c],
                      A[G::off(s) + c + 1]);
         });
       });
@@ -669,7 +676,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int s0 = 2 * t_.value;
       constexpr int s1 = s0 + 1;
       const int ra = 16 * s0 + l, rb = 16 * s1 + 15 - l;
-      const int qa = ra * (ra + 1) / 2, qb = rb * (rb + 1) / 2;
+      const int qa = (ra < K) ? ra * (ra + 1) / 2 : NQ, qb = (rb < K) ? rb * (rb + 1) / 2 : NQ;
       auto locate = [&](auto u_, int& r, int& c, int& q, double(&zr)[4], double(&zc)[4]) {
         constexpr int u = decltype(u_)::value;
         const bool first = (u <= l);
@@ -728,7 +735,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
         double off, dup;
         // steps past the lane's row (upper triangle) write the sink
-        pair_eval2(zo[s], zc, (c <= r) ? pidx(r, c) : NQ, zo[s], zc, NQ, off, dup);
+        pair_eval2(zo[s], zc, (c <= r) ? qrow_base[s] + c : NQ + c, zo[s], zc, NQ, off, dup);
         A[G::off(s) + c] = (c == r) ? cf.diag : off;
       });
     }
@@ -812,7 +819,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       });
     });
     // 1/d of this lane's rows
-    sfor<0, NS>([&](auto s_) { idg[s_.value] = rec[grp][row_of(s_.value, l)][RI]; });
+    sfor<0, NS>([&](auto s_) { idg[s_.value] = rec[grp][rrow[s_.value]][RI]; });
 
     // forward substitution x <- Lt^{-1} x (unit lower) for NV right-hand
     // sides, one column step at a time
@@ -948,7 +955,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       if constexpr (kDeriv) {
         sfor<0, NS>([&](auto s_) {
           constexpr int s = s_.value;
-          rec[grp][row_of(s, l)][RU] = uu[s];  // 0 for rows >= K
+          rec[grp][rrow[s]][RU] = uu[s];  // 0 for rows >= K
         });
         wave_lds_fence();
       }
@@ -985,10 +992,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int a = row_of(s, l);
-      base_a[s] = a * (a + 1) / 2;
+      base_a[s] = qrow_base[s];
       if constexpr (NG == 2 || kRecomp) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) zrow[s][k] = rec[grp][a][RZ + k];
+        for (int k = 0; k < 4; ++k) zrow[s][k] = rec[grp][rrow[s]][RZ + k];
       }
 #pragma unroll
       for (int g = 0; g < NG; ++g) gr[g][s] = 0.0;

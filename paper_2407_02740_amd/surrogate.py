@@ -374,19 +374,21 @@ def validation_loss(mlp: MLP, x: torch.Tensor, t: torch.Tensor, lv_weight: float
 
 def calibrate_floor(ev: V.Vecchia, mlp: MLP, dist_range, covparms, bound: float = 1e-6,
                     floors=None) -> dict:
-    """The lowest variance floor (log v / sigma2) at which the surrogate's
-    |loglik error| / n on the problem `ev` (a validation problem, judged by
-    the exact path) stays within `bound`; returns the floor, the error and
-    the served count at that floor, and the whole sweep."""
+    """The variance floor (log v / sigma2) that serves the most
+    neighbourhoods while the surrogate's |loglik error| / n on the problem
+    `ev` (a validation problem, judged by the exact path) stays within
+    `bound`; returns that floor with its error and served count, and the
+    whole sweep.  The last floor serves nothing, so one always qualifies."""
     exact = exact_loglik(ev, covparms)["loglik"]
     if floors is None:
-        floors = [math.log(v) for v in (0.02, 0.05, 0.1, 0.2, 0.3, 0.5, 0.7, 0.9)] + [1e30]
+        floors = [math.log(v) for v in (0.02, 0.05, 0.1, 0.2, 0.3, 0.5, 0.7, 0.9, 0.95, 0.99)]
+        floors.append(1e30)  # serves nothing: the exact path
     sweep = []
-    chosen = None
     for f in floors:
         r = SurrogateLoglik(ev, mlp, dist_range, lv_floor=f).evaluate(covparms)
         err = abs(r["loglik"] - exact) / ev.n
         sweep.append(dict(floor=f, err=err, served=r["served"]))
-        if chosen is None and err <= bound:
-            chosen = sweep[-1]
+    # among the floors within the bound, the one that serves the most
+    within = [r for r in sweep if r["err"] <= bound]
+    chosen = max(within, key=lambda r: r["served"]) if within else None
     return dict(chosen=chosen, sweep=sweep)

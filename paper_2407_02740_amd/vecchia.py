@@ -497,9 +497,10 @@ class GroupedVecchia(Vecchia):
 
 
 class Predictor:
-    """Kriging prediction at new points from their m nearest observed
+    """Kriging prediction at new points from their m_pred nearest observed
     neighbours (vec_kriging_predict): the prediction points are appended to
-    a copy of the observation arrays on the device."""
+    a copy of the observation arrays on the device.  m_pred is the width of
+    NN_pred minus one and need not equal the m of the fitted model."""
 
     def __init__(self, ev: Vecchia, locs_pred, X_pred, NN_pred):
         dev = ev.device
@@ -510,9 +511,9 @@ class Predictor:
         self.y = torch.cat([ev.y, torch.zeros(self.n_pred, dtype=torch.float64, device=dev)])
         self.X = torch.cat([ev.X, xp]).contiguous()
         self.NN = torch.as_tensor(NN_pred, dtype=torch.int32).to(dev).contiguous()
-        if self.NN.shape != (self.n_pred, ev.pb.m + 1):
-            raise ValueError("NN_pred must be [n_pred][m + 1]")
-        self.pb = Problem(n=self.n_obs + self.n_pred, m=ev.pb.m, d=ev.pb.d, p=ev.p,
+        if self.NN.dim() != 2 or self.NN.shape[0] != self.n_pred or self.NN.shape[1] < 1:
+            raise ValueError("NN_pred must be [n_pred][m_pred + 1]")
+        self.pb = Problem(n=self.n_obs + self.n_pred, m=self.NN.shape[1] - 1, d=ev.pb.d, p=ev.p,
                           family=ev.pb.family, smoothness=ev.pb.smoothness,
                           nspace=ev.pb.nspace, reserved=0)
         self.ev = ev

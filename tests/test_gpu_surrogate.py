@@ -2,9 +2,12 @@
 
 Network kernels (BF16 operands, FP32 accumulation) against
 oracle/mlp_oracle.py evaluated with the same BF16 rounding points: the two
-differ by FP32-versus-FP64 accumulation and by BF16 roundings that this
-flips, about 2^-9 relative on the few values it touches, so outputs are
-compared at 1e-2 of their scale and gradients blockwise at 2e-2 in norm.
+differ by FP32-versus-FP64 accumulation and by the BF16 roundings that this
+flips (one BF16 ulp, 2^-8 relative, on the values it touches), so outputs
+are compared at 1e-2 of their scale and every gradient element within
+2 * 2^-8 * (|g| + RMS of its parameter block): a flipped rounding of an
+activation moves an element by at most about one BF16 ulp of the terms it
+sums, which the block RMS bounds.
 Everything formed in FP64 (features before their BF16 rounding, surrogate
 sums, hand-back path, combine) is compared at FP64/FP32-input tolerances.
 """
@@ -78,9 +81,11 @@ def test_mlp_loss_grad_matches_oracle(rows):
     assert abs(float(loss) - ref_loss) <= 1e-2 * ref_loss
     for L, ((wo, bo), (a, b)) in enumerate(zip(MO.OFFSETS, MO.SHAPES)):
         for lo, hi, name in ((wo, wo + a * b, "W"), (bo, bo + a, "b")):
-            d = np.linalg.norm(g[lo:hi] - ref_g[lo:hi])
-            assert d <= 2e-2 * np.linalg.norm(ref_g[lo:hi]), (L, name, d,
-                                                              np.linalg.norm(ref_g[lo:hi]))
+            ref = ref_g[lo:hi]
+            rms = np.sqrt(np.mean(ref ** 2))
+            ratio = np.abs(g[lo:hi] - ref) / (np.abs(ref) + rms)
+            _say(f"grad layer {L} {name}: max |d| / (|g| + rms) = {ratio.max():.3e}")
+            assert np.all(ratio <= 2.0 * 2.0 ** -8), (L, name, ratio.max(), int(ratio.argmax()))
 
 
 def test_adam_step_matches_its_definition():
@@ -243,10 +248,82 @@ def test_training_learns_and_the_trained_network_gains():
     for row in cal["sweep"]:
         _say(f"surrogate: floor {row['floor']:.3g}: |dloglik|/n {row['err']:.3e}, "
              f"served {row['served']} of {n}")
-    assert cal["chosen"] is not None
+    # the gate takes the floor that serves the most within the bound (the
+    # last floor hands everything back, so one always qualifies)
+    within = [r for r in cal["sweep"] if r["err"] <= 1e-6]
+    assert cal["chosen"] is not None and within
+    assert cal["chosen"]["served"] == max(r["served"] for r in within)
     w2, ev2, _ = _plane(50_000, 24, covparms=(1.0, 0.1, 0.05), nu=1.5)
     r2 = SG.SurrogateLoglik(ev2, mlp, dist, lv_floor=cal["chosen"]["floor"]).evaluate(cp)
     e2 = abs(r2["loglik"] - SG.exact_loglik(ev2, cp)["loglik"]) / ev2.n
     _say(f"surrogate: held-out check at floor {cal['chosen']['floor']:.3g}: |dloglik|/n {e2:.3e},"
          f" served {r2['served']} of {ev2.n}")
     assert e2 <= 1e-6
+
+
+def test_surrogate_against_the_exact_path():
+    """What the learned surrogate gains or loses against the exact path on
+    one problem of the evaluation shape (uniform 2-D points, Matern 3/2
+    (1, 0.05, 0.05), m = 30; n = 262,144 here, the full evaluation runs in
+    the surrogate benchmark): served fraction, |dloglik| / n and time of the
+    gated and of the served-everything surrogate against the exact FP64
+    loglik pass, and the whole served-versus-error curve of the gate.  The
+    network is trained on neighbourhoods over the batched workload's
+    parameter ranges.  Measured result (recorded in the design notes): BF16
+    kriging weights carry ~1e-2 relative error, so serving even a handful of
+    neighbourhoods breaks the 1e-6 per-observation bound; the gate then hands
+    everything back and the surrogate gains nothing over the exact path.
+    Asserted: the accounting of served and handed-back observations, the
+    bound at the gate's floor, and that the gate serves the most it can
+    within the bound."""
+    _say("surrogate vs exact: training set")
+    x, raw, dist = SG.training_set(1_000_000, seed=31, log=_say)
+    lv = raw[:, SG.M]
+    shift, scale = float(lv.mean()), float(lv.std())
+    t = SG.targets_of(raw, shift, scale)
+    del raw
+    mlp = SG.MLP(seed=3, lv_shift=shift, lv_scale=scale)
+    SG.train(mlp, x, t, epochs=2, batch=4096, lr=2e-3, log=_say)
+    del x, t
+    w = S.surrogate_plane(seed=57, n=262_144)
+    n = w["n"]
+    ev = V.Vecchia(w["locs"], w["NN"], w["y"], w["X"], V.FAMILY_ISO, 1.5, 0)
+    cp = np.array(w["covparms"])
+
+    def timed(fn, reps=3):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / reps
+
+    ex, t_ex = timed(lambda: SG.exact_loglik(ev, cp))
+    cal = SG.calibrate_floor(ev, mlp, dist, cp, bound=1e-6)
+    rows = []
+    for row in cal["sweep"]:
+        r, ms = timed(lambda: SG.SurrogateLoglik(ev, mlp, dist, lv_floor=row["floor"]).evaluate(cp),
+                      reps=1)
+        assert r["served"] + r["handed_back"] == n
+        assert r["served"] == row["served"]
+        rows.append((row["floor"], r["served"] / n, row["err"], ms))
+    ra, t_all = timed(lambda: SG.SurrogateLoglik(ev, mlp, dist, lv_slack=50.0).evaluate(cp))
+    err_all = abs(ra["loglik"] - ex["loglik"]) / n
+    _say(f"surrogate vs exact: exact loglik pass {t_ex:.3f} ms")
+    _say(f"surrogate vs exact: served-all {ra['served'] / n:.4f} of n, |dloglik|/n {err_all:.3e}, "
+         f"{t_all:.3f} ms")
+    for floor, frac, err, ms in rows:
+        _say(f"surrogate vs exact: floor {floor:.3g}: served {frac:.5f} of n, |dloglik|/n "
+             f"{err:.3e}, {ms:.3f} ms")
+    ch = cal["chosen"]
+    _say(f"surrogate vs exact: gate at 1e-6 serves {ch['served']} of {n} "
+         f"(|dloglik|/n {ch['err']:.3e})")
+    assert ch["err"] <= 1e-6
+    within = [r for r in cal["sweep"] if r["err"] <= 1e-6]
+    assert ch["served"] == max(r["served"] for r in within)
+    # handing everything back reproduces the exact path
+    last = cal["sweep"][-1]
+    assert last["served"] == 0 and last["err"] <= 1e-12
