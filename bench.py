@@ -47,7 +47,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PROFILE = os.path.join(ROOT, "profiles", "sums_kernel_satellite_spacetime_n1M_m30.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_02740_amd", "csrc", f)
-                  for f in ("vecchia_kernels.hpp", "exp_table.inc")] + \
+                  for f in ("vecchia_kernels.hpp", "exp_table.inc", "dpp_fmac.inc")] + \
                  [os.path.join(ROOT, "paper_2407_02740_amd", "build.py")]
 
 

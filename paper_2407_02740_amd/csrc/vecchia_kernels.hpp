@@ -334,14 +334,15 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   const int grp = threadIdx.x >> 4;
   constexpr double kFar = 1e30;
   // Lp offsets of this lane's rows: where its row r starts (the sink for
-  // rows >= K), and its column r in the rows below
+  // rows >= K, and for row 0, which has no entries and would share its start
+  // with row 1), and its column r in the rows below
   int lrow_base[NS], lcol_base[NS];
   // and the start of its pair factors (the sink for rows >= K), and its row
   // record (the sink row for rows >= RROWS)
   int qrow_base[NS], rrow[NS];
   sfor<0, NS>([&](auto s_) {
     const int r = row_of(s_.value, lane);
-    lrow_base[s_.value] = (r < K) ? r * (r - 1) / 2 : LPN + 1;
+    lrow_base[s_.value] = (r >= 1 && r < K) ? r * (r - 1) / 2 : LPN + 1;
     lcol_base[s_.value] = r;
     qrow_base[s_.value] = (r < K) ? r * (r + 1) / 2 : NQ;
     rrow[s_.value] = (r < RROWS) ? r : RROWS;
@@ -856,8 +857,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // entries at c >= r (zeros) run into the rows after r, at smaller
     // columns.  Slots are stored in increasing row order and columns in
     // decreasing order, so every such spill-over is overwritten later by the
-    // entry that belongs there; rows >= K write a sink.  No address
-    // arithmetic or select per entry.
+    // entry that belongs there (row r >= 1 spills into row r' > r at a
+    // column at least r smaller, never within the same store); rows >= K and
+    // row 0 write a sink.  No address arithmetic or select per entry.
     if constexpr (!kLik && !kRowBack) {
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
