@@ -48,11 +48,16 @@ extern "C" {
 /* Number of network parameters (FP32 and BF16 arrays hold this many). */
 int64_t vec_mlp_param_count(void);
 
-/* Device workspace bytes for `rows` rows of vec_mlp_forward (training = 0)
- * or vec_mlp_loss_grad (training != 0); 0 if rows is invalid. */
+/* Device workspace bytes for `rows` rows of vec_mlp_forward (training = 0:
+ * a copy of the weights, whatever the row count) or vec_mlp_loss_grad
+ * (training != 0); 0 if rows is invalid. */
 size_t vec_mlp_workspace_bytes(int64_t rows, int32_t training);
 
-/* y[rows][OUT] (FP32) = network(x[rows][IN] (BF16)). */
+/* y[rows][OUT] (FP32) = network(x[rows][IN] (BF16)): the weights are copied
+ * into the workspace in the order the matrix-core operands take them, then
+ * the whole network runs in one launch.  rows: a positive multiple of 32, at
+ * most 2^24.  x, params, y and workspace 16-byte aligned (VEC_EINVAL
+ * otherwise). */
 int vec_mlp_forward(int64_t rows, const uint16_t* x, const float* params,
                     const uint16_t* params_bf16, float* y, void* workspace,
                     size_t workspace_bytes, void* stream);
@@ -79,7 +84,8 @@ int vec_mlp_to_bf16(const float* params, uint16_t* params_bf16, void* stream);
  * m = VEC_SURROGATE_M: features[(i - i0)][IN] (BF16).  flag[(i - i0)] (may
  * be NULL) = 1 for observations the network must not serve: i < m, a
  * malformed NNarray row, or a neighbour offset whose scaled length lies
- * outside [dist_lo, dist_hi] (the geometry the network was trained on). */
+ * outside [dist_lo, dist_hi] (the geometry the network was trained on).
+ * features 16-byte aligned (VEC_EINVAL otherwise). */
 int vec_surrogate_features(const vec_problem* pb, const double* locs, const int32_t* NNarray,
                            const double* covparms, int64_t i0, int64_t i1, float dist_lo,
                            float dist_hi, uint16_t* features, uint8_t* flag, void* stream);
@@ -89,7 +95,8 @@ size_t vec_surrogate_workspace_bytes(const vec_problem* pb);
 
 /* FP64 sums of vec_loglik (logdet, ySy, XSX, ySX; 2 + p*p + p doubles) over
  * the observations of [i0, i1) that the network serves, from its outputs
- * pred[(i - i0)][OUT]: with b = pred[..][0..m-1] and
+ * pred[(i - i0)][OUT] (16-byte aligned, VEC_EINVAL otherwise): with
+ * b = pred[..][0..m-1] and
  * lv = pred[..][m] * lv_scale + lv_shift, the residuals are
  * e_y = y_i - b.y_s and e_X = X_i - b.X_s and the variance is
  * v = sigma2 exp(lv).  An observation is handed back instead (its index
