@@ -62,9 +62,18 @@ def algorithmic_flops(k: int, d: int, p: int, R: int) -> int:
     derivative entries 3k(k+1)/2, the symmetric product 2k^2 and a forward
     solve k^2, the nugget solve k^2, the residual derivatives
     (R + 2) 2k(1 + p) and the information (R + 2)(R + 3) k."""
-    return int(k * (k - 1) // 2 * (3 * d + 2) + k ** 3 / 3 + (1 + p) * k * k + k * k
-               + R * (3 * k * (k + 1) // 2 + 3 * k * k) + k * k + (R + 2) * 2 * k * (1 + p)
-               + (R + 2) * (R + 3) * k)
+    return algorithmic_flops_block(k, 1, d, p, R)
+
+
+def algorithmic_flops_block(k: int, b: int, d: int, p: int, R: int) -> int:
+    """The same count for a block of b observations conditioned jointly
+    (grouped Vecchia; k = conditioning set + b): the terms that act on the
+    self vector u (its back solve, the per-range products and solves, the
+    nugget solve, the residual derivatives and the information) are needed
+    once per block member."""
+    return int(k * (k - 1) // 2 * (3 * d + 2) + k ** 3 / 3 + (1 + p) * k * k + b * k * k
+               + R * (3 * k * (k + 1) // 2 + 3 * b * k * k) + b * k * k
+               + b * (R + 2) * 2 * k * (1 + p) + b * (R + 2) * (R + 3) * k)
 
 
 def kernel_source_hash() -> str:
@@ -888,6 +897,25 @@ def bench_grouped(args):
         evs = V.Vecchia(p2, NN, y2, X, V.FAMILY_ISO, 1.5)
     tss, _ = timed(evs)
     log(f"grouped step {tgs * 1e3:.3f} ms, ungrouped step {tss * 1e3:.3f} ms")
+    # the grouped sums alone (wave kernel and its device reduction), HIP
+    # events on their stream; algorithmic flops summed over the blocks
+    with torch.cuda.stream(stream):
+        cpg = evg.covparms(cp0)
+        evg.raw_sums(cpg, check=False)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            evg.raw_sums(cpg, check=False)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    evg.check_status("kernel timing")
+    kernel_ms = e0.elapsed_time(e1) / args.kernel_reps
+    bsz = np.diff(np.asarray(bs, dtype=np.int64))
+    ksz = np.diff(np.asarray(cs, dtype=np.int64)) + bsz
+    F = sum(algorithmic_flops_block(int(k), int(b), 2, 1, 1) for k, b in zip(ksz, bsz))
+    achieved = F / (kernel_ms * 1e-3) / 1e12
+    log(f"grouped sums {kernel_ms:.4f} ms, {F:.4e} flop -> {achieved:.2f} TFLOP/s")
     line = {
         "metric": "observations/s (grouped loglik+grad+Fisher), n=262144, blocks <= 4, m=30",
         "value": n / tgs, "unit": "observations/s", "n_gpus": 1, "steps": args.steps,
@@ -896,9 +924,13 @@ def bench_grouped(args):
         "config": {"workload": "grouped_plane", "n": n, "m": m, "max_block": g,
                    "blocks": int(len(bs) - 1), "covariance": "Matern 3/2 (1.0, 0.05, 0.05)",
                    "step": "Fisher-scoring iteration of the grouped likelihood, HIP graph"},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": None},
+        "cpu_baseline": None,
         "detail": {"ungrouped_step_ms": 1e3 * tss, "ungrouped_obs_per_s": n / tss,
-                   "grouped_loglik": resg["loglik"]},
+                   "grouped_loglik": resg["loglik"], "grouped_sums_ms": kernel_ms,
+                   "flop_per_step": F},
     }
     print(json.dumps(line), flush=True)
 

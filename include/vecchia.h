@@ -292,7 +292,13 @@ int vec_ordered_nn(int64_t n, int32_t d, int32_t m, const double* locs, int32_t*
  * apply.  Limits: max_block <= 8, pb->m + max_block <= 64, d <= 4 when
  * max_block > 1, 1 + p + (P - 1) max_block <= 64.  A block that breaks
  * them, or an index out of range, sets VEC_FLAG_BADNN with the block's
- * first observation.  workspace: vec_grouped_workspace_bytes(pb, nblocks). */
+ * first observation.  Where pb->m + max_block - 1 <= 60 and the family is
+ * isotropic or space-time with time last, the sums run on the fused kernel
+ * as one-observation conditionals (member k of a block conditioned on the
+ * block's set and members 0..k-1: the same density and expected
+ * information); a conditioning set longer than the observations before its
+ * block is then also flagged.  workspace: vec_grouped_workspace_bytes(pb,
+ * nblocks), which covers every max_block. */
 size_t vec_grouped_workspace_bytes(const vec_problem* pb, int64_t nblocks);
 int vec_grouped_raw_sums(const vec_problem* pb, const double* locs, const double* y,
                          const double* X, const double* covparms, int64_t nblocks,

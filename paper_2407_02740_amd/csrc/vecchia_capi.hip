@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -524,10 +525,11 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
                               const double* covparms, const double* beta, int64_t i0, int64_t i1,
                               double* partials, size_t partials_bytes, int* grid_out,
                               int32_t* status, hipStream_t st, double* rows_out = nullptr,
-                              const int32_t* index = nullptr, int64_t nn_row0 = 0) {
+                              const int32_t* index = nullptr, int64_t nn_row0 = 0,
+                              bool short_rows = false) {
   if (dm.wave) {
     // the sums of Algorithm 1 with their derivatives and information only
-    if (mode != kModeSums || rows_out || index || nn_row0 != 0) return VEC_EINVAL;
+    if (mode != kModeSums || rows_out || index || nn_row0 != 0 || short_rows) return VEC_EINVAL;
     const int grid = vecchia_wave::wave_grid(i1 - i0);
     *grid_out = grid;
     if (grid == 0) return VEC_OK;
@@ -577,6 +579,7 @@ static int enqueue_block_sums(const vec_problem* pb, const Dims& dm, int mode, c
   args.index = index;
   args.n = pb->n;
   args.nn_row0 = nn_row0;
+  args.short_rows = short_rows ? 1 : 0;
   return hip_code(kLaunch[dm.kidx][pc][ng][mode](grid, st, args));
 }
 
@@ -587,7 +590,7 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
                         double* raw, void* workspace, size_t workspace_bytes, int32_t* status,
                         hipStream_t st, double* rows_out = nullptr,
                         const int32_t* index = nullptr,
-                        int64_t nn_row0 = 0) {
+                        int64_t nn_row0 = 0, bool short_rows = false) {
   const int64_t total = i1 - i0;
   const int nraw = nraw_for(dm, mode);
   if (total == 0) {
@@ -597,7 +600,8 @@ static int enqueue_sums(const vec_problem* pb, const Dims& dm, int mode, const d
   double* partials = static_cast<double*>(workspace);
   int grid = 0;
   int rc = enqueue_block_sums(pb, dm, mode, locs, NN, y, X, covparms, beta, i0, i1, partials,
-                              workspace_bytes, &grid, status, st, rows_out, index, nn_row0);
+                              workspace_bytes, &grid, status, st, rows_out, index, nn_row0,
+                              short_rows);
   if (rc != VEC_OK) return rc;
   hipLaunchKernelGGL(reduce_kernel, dim3(nraw), dim3(256), 0, st, partials, grid, nraw, raw);
   return hip_code(hipGetLastError());
@@ -707,7 +711,72 @@ static int check_batch_call(const vec_batch* bt, const vec_batch_plan* plan, con
   return VEC_OK;
 }
 
-// Grouped sums: one wave per block, then the fixed-order reduction.
+// Grouped sums on the fused kernel.  A block's conditional density
+// p(y_B | y_N) is the product of its members' one-observation conditionals,
+// member k conditioned on N and on members 0..k-1 (the chain rule of the
+// Gaussian density, exact), and the expected information of the block
+// conditional is the sum of theirs (each factor's score has mean zero given
+// everything the later factors condition on).  So the block's raw sums are
+// those of ordinary neighbourhoods whose NNarray rows list N and the earlier
+// members: row i of the expanded array (width m + max_block) holds i, the
+// block's conditioning set, the members before i, then -1.  Rows of
+// observations outside every block keep -1 in column 0 and are skipped.
+__global__ void grouped_clear_rows_kernel(int64_t n, int width, int32_t* __restrict__ NN) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    NN[i * width] = -1;
+}
+
+__global__ void grouped_expand_kernel(int64_t nblocks, const int64_t* __restrict__ block_start,
+                                      const int64_t* __restrict__ cond_start,
+                                      const int32_t* __restrict__ cond, int64_t ncond, int m,
+                                      int gmax, int64_t n, int width, int32_t* __restrict__ NN,
+                                      int32_t* __restrict__ status) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  const int64_t first = block_start[b], last = block_start[b + 1];
+  const int64_t c0 = cond_start[b], c1 = cond_start[b + 1];
+  bool ok = first >= 0 && last > first && last - first <= gmax && last <= n && c0 >= 0 &&
+            c1 >= c0 && c1 <= ncond && c1 - c0 <= m;
+  if (!ok) {
+    atomicOr(&status[0], VEC_FLAG_BADNN);
+    atomicMin(&status[1], (int32_t)(first > 0 ? first : 0));
+    return;
+  }
+  // indices are earlier observations, at most `first` distinct ones
+  for (int64_t k = c0; k < c1; ++k) ok = ok && cond[k] >= 0 && (int64_t)cond[k] < first;
+  if (!ok || c1 - c0 > first) {
+    atomicOr(&status[0], VEC_FLAG_BADNN);
+    atomicMin(&status[1], (int32_t)first);
+    return;
+  }
+  for (int64_t i = first; i < last; ++i) {
+    int32_t* row = NN + i * width;
+    int col = 0;
+    row[col++] = (int32_t)i;
+    for (int64_t k = c0; k < c1; ++k) row[col++] = cond[k];
+    for (int64_t j = first; j < i; ++j) row[col++] = (int32_t)j;
+    while (col < width) row[col++] = -1;
+  }
+}
+
+// The problem whose neighbourhoods are the expanded rows, if the fused
+// kernel takes it (family and split it serves, m + max_block - 1 <= 60).
+static bool grouped_fused_dims(const vec_problem* pb, int32_t max_block, vec_problem* q,
+                               Dims* dq) {
+  *q = *pb;
+  q->m = pb->m + max_block - 1;
+  return dims_of(q, dq) && !dq->wave;
+}
+
+static size_t grouped_fused_bytes(const vec_problem* q, const Dims& dq) {
+  const int grid = grid_for(q->n);
+  return align256((size_t)q->n * (q->m + 1) * sizeof(int32_t)) +
+         (size_t)(grid > 0 ? grid : 1) * dq.nraw * sizeof(double);
+}
+
+// Grouped sums: the fused kernel over the expanded rows where it applies,
+// else one wave per block; then the fixed-order reduction.
 static int check_grouped(const vec_problem* pb, const Dims& dm, int64_t nblocks, int32_t max_block) {
   if (nblocks < 0 || max_block < 1 || max_block > vecchia_wave::kMaxBlock) return VEC_EINVAL;
   if (max_block > 1 && pb->d > 4) return VEC_EINVAL;
@@ -725,6 +794,22 @@ static int enqueue_grouped_sums(const vec_problem* pb, const Dims& dm, const dou
   if (nblocks == 0) {
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, raw, dm.nraw, 0.0);
     return hip_code(hipGetLastError());
+  }
+  vec_problem q;
+  Dims dq;
+  if (grouped_fused_dims(pb, max_block, &q, &dq)) {
+    if (!workspace || workspace_bytes < grouped_fused_bytes(&q, dq)) return VEC_EWORKSPACE;
+    const int width = q.m + 1;
+    int32_t* NNx = static_cast<int32_t*>(workspace);
+    const size_t nnb = align256((size_t)q.n * width * sizeof(int32_t));
+    hipLaunchKernelGGL(grouped_clear_rows_kernel, dim3(1024), dim3(256), 0, st, q.n, width, NNx);
+    hipLaunchKernelGGL(grouped_expand_kernel, dim3((unsigned)((nblocks + 255) / 256)), dim3(256),
+                       0, st, nblocks, block_start, cond_start, cond, ncond, pb->m, max_block,
+                       q.n, width, NNx, status);
+    if (hipGetLastError() != hipSuccess) return VEC_EHIP;
+    return enqueue_sums(&q, dq, kModeSums, locs, NNx, y, X, covparms, nullptr, 0, q.n, raw,
+                        static_cast<char*>(workspace) + nnb, workspace_bytes - nnb, status, st,
+                        nullptr, nullptr, 0, true);
   }
   const int grid = vecchia_wave::wave_grid(nblocks);
   if (!workspace || workspace_bytes < (size_t)grid * dm.nraw * sizeof(double))
@@ -1073,7 +1158,14 @@ size_t vec_grouped_workspace_bytes(const vec_problem* pb, int64_t nblocks) {
   Dims dm;
   if (!dims_of(pb, &dm) || nblocks < 0) return 0;
   const int grid = vecchia_wave::wave_grid(nblocks);
-  return (size_t)(grid > 0 ? grid : 1) * dm.nraw * sizeof(double);
+  size_t bytes = (size_t)(grid > 0 ? grid : 1) * dm.nraw * sizeof(double);
+  // the fused route for any block size it serves
+  for (int32_t g = 1; g <= vecchia_wave::kMaxBlock; ++g) {
+    vec_problem q;
+    Dims dq;
+    if (grouped_fused_dims(pb, g, &q, &dq)) bytes = std::max(bytes, grouped_fused_bytes(&q, dq));
+  }
+  return bytes;
 }
 
 int vec_grouped_raw_sums(const vec_problem* pb, const double* locs, const double* y,

@@ -270,6 +270,10 @@ struct SumsArgs {
   const int32_t* index;    // optional: observations at positions [i0, i1) of this list
   int64_t n;               // observations of the problem (bounds of index entries)
   int64_t nn_row0;         // observation whose NNarray row is NN[0] (0: the whole array)
+  // short_rows != 0: a -1 among the first min(i, m) neighbour columns is a
+  // missing neighbour (a padding row), and a row whose column 0 is -1 is
+  // skipped (it contributes nothing and is not an error)
+  int32_t short_rows;
   BatchClass batch;
 };
 
@@ -412,18 +416,20 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // 1..q of the NNarray row are read (column 0 otherwise).  Neighbours are
   // earlier observations; rows appended after the observed ones (nn_row0 >
   // 0, prediction points) may only name observed points j < nn_row0.
-  auto fetch_ids = [&](int64_t ii, int lan, int64_t(&id)[NS], bool& bad) {
-    const int qq = (int)(ii < (int64_t)m ? ii : (int64_t)m);
+  auto fetch_ids = [&](int64_t ii, int lan, int64_t(&id)[NS], bool& bad, bool& skip) {
     const int32_t* row = NN + (ii - a.nn_row0) * (int64_t)(m + 1);
+    const int32_t head = row[0];
+    skip = a.short_rows && head == -1;
+    const int qq = skip ? 0 : (int)(ii < (int64_t)m ? ii : (int64_t)m);
     const int64_t jend = (a.nn_row0 > 0) ? a.nn_row0 : ii;
-    bad = (row[0] != (int32_t)ii);
+    bad = !skip && (head != (int32_t)ii);
     sfor<0, NS>([&](auto s_) {
       constexpr int s = s_.value;
       const int r = row_of(s, lan);
       const bool nb = r < qq;
       const int64_t j = row[nb ? 1 + r : 0];
       const bool okj = (j >= 0) && (j < jend);
-      bad = bad || (nb && !okj);
+      bad = bad || (nb && !okj && !(a.short_rows && j == -1));
       id[s] = (r == K - 1) ? ii : ((nb && okj) ? j : (int64_t)-1);
     });
   };
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // is loaded at the top of an iteration and the next coordinates, y and X
   // after phase 1, so each gather finds its inputs in registers.
   int64_t idc[NS];
-  bool badc = false;
+  bool badc = false, skipc = false;
   double zv[NS][4], yv[NS], xv[NS][PC];
 
   // sums of the groups (logdet from the running product) into one row of
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   set_params();
   if (first < total) {
     const int64_t ii = obs_of(first);
-    fetch_ids(ii, lane, idc, badc);
+    fetch_ids(ii, lane, idc, badc, skipc);
     fetch_vals(ii, idc, zv, yv, xv);
   }
 
@@ -526,7 +532,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // lane-dependent predicates from being hoisted out of the loop
     int l = lane;
     asm volatile("" : "+v"(l));
-    const bool active = base + grp < total;
+    const bool active = base + grp < total && !skipc;
     const int64_t i = obs_of(base);
     const bool badidx = index_bad(base);
     const int q = (int)(i < (int64_t)m ? i : (int64_t)m);
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     const int64_t inext = more ? obs_of(base + stride) : i;
     int64_t idn[NS];
     sfor<0, NS>([&](auto s_) { idn[s_.value] = -1; });
-    bool badn = false;
+    bool badn = false, skipn = false;
     bool badnn = badc;
     bool badval = false;
 
@@ -575,7 +581,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       }
     });
     // next NNarray row, in flight during phase 1
-    if (more) fetch_ids(inext, l, idn, badn);
+    if (more) fetch_ids(inext, l, idn, badn, skipn);
     wave_lds_fence();
 
     // Covariance of two pairs of scaled locations (evaluated side by side so
@@ -585,8 +591,13 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     //   sigma2 e^-h = 2^m * T[j] * (1 + q),  T[j] = sigma2 2^(j/64),
     //   q = r + r^2/2 + ... + r^5/120 (truncation below 4e-17 relative),
     // formed as T + T q; -h is clamped at -800 so that 2^m underflows to 0.
-    auto pair_eval2 = [&](const double* za0, const double* zb0, int idx0, const double* za1,
-                          const double* zb1, int idx1, double& v0, double& v1) {
+    // kExpo (smoothness 1/2): f = e^-h and -f'(h)/h = e^-h / h, the general
+    // forms with c1 = c2 = a0 = a1 = 0 and a2 = 1 written without their
+    // zero terms (the same values bit for bit).
+    auto pair_eval2 = [&](auto expo_, const double* za0, const double* zb0, int idx0,
+                          const double* za1, const double* zb1, int idx1, double& v0,
+                          double& v1) {
+      constexpr bool kExpo = decltype(expo_)::value;
       double h20 = kH2Floor, h21 = kH2Floor;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -616,8 +627,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       q1 *= r1;
       const double sE0 = ldexp(__builtin_fma(T0, q0, T0), i0n >> 6);
       const double sE1 = ldexp(__builtin_fma(T1, q1, T1), i1n >> 6);
-      const double sF0 = sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
-      const double sF1 = sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
+      const double sF0 = kExpo ? sE0 * hi0
+                               : sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
+      const double sF1 = kExpo ? sE1 * hi1
+                               : sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
       if constexpr (kStoreF) {
         // isotropic: the finished dSigma/drho entry, sF h^2 / rho (h^2 without
         // the floor, so that it is exactly 0 on the diagonal and at
@@ -625,8 +638,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         sfv[grp][idx0] = (NG == 1) ? sF0 * (h20 - kH2Floor) * cf.ir[0] : sF0;
         sfv[grp][idx1] = (NG == 1) ? sF1 * (h21 - kH2Floor) * cf.ir[0] : sF1;
       }
-      v0 = sE0 * __builtin_fma(hh0, __builtin_fma(hh0, cf.c2, cf.c1), 1.0);
-      v1 = sE1 * __builtin_fma(hh1, __builtin_fma(hh1, cf.c2, cf.c1), 1.0);
+      v0 = kExpo ? sE0 : sE0 * __builtin_fma(hh0, __builtin_fma(hh0, cf.c2, cf.c1), 1.0);
+      v1 = kExpo ? sE1 : sE1 * __builtin_fma(hh1, __builtin_fma(hh1, cf.c2, cf.c1), 1.0);
     };
     auto pidx = [](int r, int c) { return r * (r + 1) / 2 + c; };
 
@@ -637,6 +650,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     // step may write its value into both candidate registers.
     double A[NL];
     sfor<0, NL>([&](auto e_) { A[e_.value] = 0.0; });
+    // one copy of the phase for smoothness 1/2 and one for the others
+    auto phase1 = [&](auto expo_) {
     // off-diagonal 16x16 blocks: slot s rows x columns of block t < s, two
     // columns per step, partner coordinates read one step ahead
     sfor<1, NS>([&](auto s_) {
@@ -665,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
             }
           }
           const int r = row_of(s, l);
-          pair_eval2(zo[s], zc[0], qrow_base[s] + c, zo[s], zc[1], qrow_base[s] + c + 1, A[G::off(s) + c],
+          pair_eval2(expo_, zo[s], zc[0], qrow_base[s] + c, zo[s], zc[1], qrow_base[s] + c + 1, A[G::off(s) + c],
                      A[G::off(s) + c + 1]);
         });
       });
@@ -715,12 +730,12 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         if constexpr (u + 3 < 17) locate(std::integral_constant<int, u + 3>{}, rn[1], cn[1], qn[1], zrn[1], zcn[1]);
         double off0, off1;
         if constexpr (u + 1 < 17) {
-          pair_eval2(zr[0], zc[0], q[0], zr[1], zc[1], q[1], off0, off1);
+          pair_eval2(expo_, zr[0], zc[0], q[0], zr[1], zc[1], q[1], off0, off1);
           store(std::integral_constant<int, u>{}, r[0], c[0], off0);
           store(std::integral_constant<int, u + 1>{}, r[1], c[1], off1);
         } else {
           // last (odd) step: the second slot of the evaluation repeats it
-          pair_eval2(zr[0], zc[0], q[0], zr[0], zc[0], q[0], off0, off1);
+          pair_eval2(expo_, zr[0], zc[0], q[0], zr[0], zc[0], q[0], off0, off1);
           store(std::integral_constant<int, u>{}, r[0], c[0], off0);
         }
       });
@@ -736,10 +751,17 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         for (int k = 0; k < 4; ++k) zc[k] = rec[grp][c][RZ + k];
         double off, dup;
         // steps past the lane's row (upper triangle) write the sink
-        pair_eval2(zo[s], zc, (c <= r) ? qrow_base[s] + c : NQ + c, zo[s], zc, NQ, off, dup);
+        pair_eval2(expo_, zo[s], zc, (c <= r) ? qrow_base[s] + c : NQ + c, zo[s], zc, NQ, off,
+                   dup);
         A[G::off(s) + c] = (c == r) ? cf.diag : off;
       });
     }
+    };
+    // (the 61-row kernels, at the register limit already, keep one copy)
+    if (K <= 41 && nu == 0)
+      phase1(std::true_type{});
+    else
+      phase1(std::false_type{});
 
     VEC_MARK("cholesky");
     VEC_TMARK(3);
@@ -1330,6 +1352,7 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
     }
     sfor<0, NS>([&](auto s_) { idc[s_.value] = idn[s_.value]; });
     badc = badn;
+    skipc = skipn;
     wave_lds_fence();
   }
   if constexpr (BATCH) {
