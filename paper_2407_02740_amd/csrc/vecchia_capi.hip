@@ -727,36 +727,50 @@ __global__ void grouped_clear_rows_kernel(int64_t n, int width, int32_t* __restr
     NN[i * width] = -1;
 }
 
-__global__ void grouped_expand_kernel(int64_t nblocks, const int64_t* __restrict__ block_start,
-                                      const int64_t* __restrict__ cond_start,
-                                      const int32_t* __restrict__ cond, int64_t ncond, int m,
-                                      int gmax, int64_t n, int width, int32_t* __restrict__ NN,
-                                      int32_t* __restrict__ status) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= nblocks) return;
+// one wave per block: the block's rows are one contiguous span of the
+// expanded array, written by consecutive lanes
+__global__ __launch_bounds__(64) void grouped_expand_kernel(
+    const int64_t* __restrict__ block_start, const int64_t* __restrict__ cond_start,
+    const int32_t* __restrict__ cond, int64_t ncond, int m, int gmax, int64_t n, int width,
+    int32_t* __restrict__ NN, int32_t* __restrict__ status) {
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
   const int64_t first = block_start[b], last = block_start[b + 1];
   const int64_t c0 = cond_start[b], c1 = cond_start[b + 1];
-  bool ok = first >= 0 && last > first && last - first <= gmax && last <= n && c0 >= 0 &&
-            c1 >= c0 && c1 <= ncond && c1 - c0 <= m;
+  const bool ok = first >= 0 && last > first && last - first <= gmax && last <= n && c0 >= 0 &&
+                  c1 >= c0 && c1 <= ncond && c1 - c0 <= m;
   if (!ok) {
-    atomicOr(&status[0], VEC_FLAG_BADNN);
-    atomicMin(&status[1], (int32_t)(first > 0 ? first : 0));
+    if (lane == 0) {
+      atomicOr(&status[0], VEC_FLAG_BADNN);
+      atomicMin(&status[1], (int32_t)(first > 0 ? first : 0));
+    }
     return;
   }
   // indices are earlier observations, at most `first` distinct ones
-  for (int64_t k = c0; k < c1; ++k) ok = ok && cond[k] >= 0 && (int64_t)cond[k] < first;
-  if (!ok || c1 - c0 > first) {
-    atomicOr(&status[0], VEC_FLAG_BADNN);
-    atomicMin(&status[1], (int32_t)first);
+  bool bad = false;
+  for (int64_t q = c0 + lane; q < c1; q += 64) bad = bad || cond[q] < 0 || (int64_t)cond[q] >= first;
+  if (__ballot(bad) != 0ull || c1 - c0 > first) {
+    if (lane == 0) {
+      atomicOr(&status[0], VEC_FLAG_BADNN);
+      atomicMin(&status[1], (int32_t)first);
+    }
     return;
   }
-  for (int64_t i = first; i < last; ++i) {
-    int32_t* row = NN + i * width;
-    int col = 0;
-    row[col++] = (int32_t)i;
-    for (int64_t k = c0; k < c1; ++k) row[col++] = cond[k];
-    for (int64_t j = first; j < i; ++j) row[col++] = (int32_t)j;
-    while (col < width) row[col++] = -1;
+  const int c = (int)(c1 - c0);
+  const int64_t total = (last - first) * width;
+  int32_t* span = NN + first * width;
+  for (int64_t e = lane; e < total; e += 64) {
+    const int k = (int)(e / width), col = (int)(e % width);
+    int32_t v;
+    if (col == 0)
+      v = (int32_t)(first + k);
+    else if (col <= c)
+      v = cond[c0 + col - 1];
+    else if (col <= c + k)
+      v = (int32_t)(first + (col - 1 - c));
+    else
+      v = -1;
+    span[e] = v;
   }
 }
 
@@ -776,7 +790,11 @@ static size_t grouped_fused_bytes(const vec_problem* q, const Dims& dq) {
 }
 
 // Grouped sums: the fused kernel over the expanded rows where it applies,
-// else one wave per block; then the fixed-order reduction.
+// else one wave per block; then the fixed-order reduction.  Fisher scoring
+// expands the rows once (they do not depend on the parameters) and sums
+// each iteration.
+enum GroupedStep { kGroupedExpandAndSum = 0, kGroupedExpand = 1, kGroupedSum = 2 };
+
 static int check_grouped(const vec_problem* pb, const Dims& dm, int64_t nblocks, int32_t max_block) {
   if (nblocks < 0 || max_block < 1 || max_block > vecchia_wave::kMaxBlock) return VEC_EINVAL;
   if (max_block > 1 && pb->d > 4) return VEC_EINVAL;
@@ -790,8 +808,10 @@ static int enqueue_grouped_sums(const vec_problem* pb, const Dims& dm, const dou
                                 int64_t nblocks, const int64_t* block_start,
                                 const int64_t* cond_start, const int32_t* cond, int64_t ncond,
                                 int32_t max_block, double* raw, void* workspace,
-                                size_t workspace_bytes, int32_t* status, hipStream_t st) {
+                                size_t workspace_bytes, int32_t* status, hipStream_t st,
+                                GroupedStep step = kGroupedExpandAndSum) {
   if (nblocks == 0) {
+    if (step == kGroupedExpand) return VEC_OK;
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, raw, dm.nraw, 0.0);
     return hip_code(hipGetLastError());
   }
@@ -802,15 +822,19 @@ static int enqueue_grouped_sums(const vec_problem* pb, const Dims& dm, const dou
     const int width = q.m + 1;
     int32_t* NNx = static_cast<int32_t*>(workspace);
     const size_t nnb = align256((size_t)q.n * width * sizeof(int32_t));
-    hipLaunchKernelGGL(grouped_clear_rows_kernel, dim3(1024), dim3(256), 0, st, q.n, width, NNx);
-    hipLaunchKernelGGL(grouped_expand_kernel, dim3((unsigned)((nblocks + 255) / 256)), dim3(256),
-                       0, st, nblocks, block_start, cond_start, cond, ncond, pb->m, max_block,
-                       q.n, width, NNx, status);
-    if (hipGetLastError() != hipSuccess) return VEC_EHIP;
+    if (step != kGroupedSum) {
+      hipLaunchKernelGGL(grouped_clear_rows_kernel, dim3(1024), dim3(256), 0, st, q.n, width, NNx);
+      hipLaunchKernelGGL(grouped_expand_kernel, dim3((unsigned)nblocks), dim3(64), 0, st,
+                         block_start, cond_start, cond, ncond, pb->m, max_block, q.n, width, NNx,
+                         status);
+      if (hipGetLastError() != hipSuccess) return VEC_EHIP;
+      if (step == kGroupedExpand) return VEC_OK;
+    }
     return enqueue_sums(&q, dq, kModeSums, locs, NNx, y, X, covparms, nullptr, 0, q.n, raw,
                         static_cast<char*>(workspace) + nnb, workspace_bytes - nnb, status, st,
                         nullptr, nullptr, 0, true);
   }
+  if (step == kGroupedExpand) return VEC_OK;  // the wave kernel reads the blocks directly
   const int grid = vecchia_wave::wave_grid(nblocks);
   if (!workspace || workspace_bytes < (size_t)grid * dm.nraw * sizeof(double))
     return VEC_EWORKSPACE;
@@ -1198,10 +1222,16 @@ int vec_grouped_fisher_fit(const vec_problem* pb, const double* locs, const doub
   if (!locs || !y || !X || !covparms || !raw || !out || !status || ncond < 0) return VEC_EINVAL;
   if (nblocks > 0 && (!block_start || !cond_start || (ncond > 0 && !cond))) return VEC_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (iters > 0) {
+    rc = enqueue_grouped_sums(pb, dm, locs, y, X, covparms, nblocks, block_start, cond_start, cond,
+                              ncond, max_block, raw, workspace, workspace_bytes, status, st,
+                              kGroupedExpand);
+    if (rc != VEC_OK) return rc;
+  }
   auto one = [&]() -> int {
     int r = enqueue_grouped_sums(pb, dm, locs, y, X, covparms, nblocks, block_start, cond_start,
                                  cond, ncond, max_block, raw, workspace, workspace_bytes, status,
-                                 st);
+                                 st, kGroupedSum);
     if (r != VEC_OK) return r;
     enqueue_combine(pb, dm, raw, out, status, st);
     enqueue_fisher(dm, out, covparms, status, max_step, st);
