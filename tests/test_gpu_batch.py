@@ -148,9 +148,10 @@ def test_batch_fisher_fit_matches_oracle(use_graph):
 @pytest.mark.skipif(os.environ.get("VECCHIA_SKIP_FULL") == "1", reason="full size skipped")
 def test_full_size_batched_uneven():
     """512 datasets, about 1.3e7 neighbourhoods, in the benchmark's launch
-    configuration: sampled datasets of every size class against the oracle,
-    every dataset against the single-problem kernel (itself checked against
-    the oracle at full size)."""
+    configuration: 32 sampled datasets (eight of every size class, its
+    smallest and largest among them) against the oracle, every dataset
+    against the single-problem kernel (itself checked against the oracle at
+    full size)."""
     _say("full batched: generating")
     w = S.batched_uneven()
     _say(f"full batched: {w['nsets']} datasets, {int(w['n'].sum())} observations")
@@ -159,7 +160,15 @@ def test_full_size_batched_uneven():
         vb = _vb(w)
         out = vb.loglik_grad_info(w["covparms"]).cpu().numpy()
     torch.cuda.synchronize()
-    picks = [int(np.flatnonzero(w["m"] == m)[0]) for m in (10, 20, 30, 40)]
+    # per size class: its smallest and largest dataset and six more drawn
+    # with a fixed seed (32 of the 512 against the oracle)
+    rng = np.random.default_rng(149)
+    picks = []
+    for m in (10, 20, 30, 40):
+        members = np.flatnonzero(w["m"] == m)
+        by_n = members[np.argsort(w["n"][members], kind="stable")]
+        extra = rng.choice(by_n[1:-1], size=min(6, len(by_n) - 2), replace=False)
+        picks += [int(by_n[0]), int(by_n[-1])] + [int(b) for b in extra]
     for b in picks:
         _say(f"full batched: oracle on dataset {b} (n={w['n'][b]}, m={w['m'][b]})")
         check_outputs(V.unpack_out(out[b], 1, vb.P), _oracle_member(w, b), f"full {b}")
