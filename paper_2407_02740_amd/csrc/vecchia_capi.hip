@@ -34,6 +34,9 @@ VEC_DECLARE_K(21);
 VEC_DECLARE_K(31);
 VEC_DECLARE_K(41);
 #define VEC_DECLARE_SINGLE(K, PC, NG, MODE, B) extern template VECCHIA_LAUNCH_SIG(K, PC, NG, MODE, B)
+VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 35, 1);
+VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 35, 2);
+VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 35, 3);
 VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 1);
 VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 2);
 VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 3);
@@ -45,8 +48,8 @@ VECCHIA_FOR_SINGLE(VEC_DECLARE_SINGLE, 61, 3);
 #define VEC_PC(K, PC) {VEC_NG(K, PC, 1), VEC_NG(K, PC, 2)}
 #define VEC_ROW(K) {VEC_PC(K, 1), VEC_PC(K, 2), VEC_PC(K, 3)}
 constexpr int kNumModes = 4;
-static const launch_fn kLaunch[kNumK][3][2][kNumModes] = {VEC_ROW(11), VEC_ROW(21), VEC_ROW(31),
-                                                           VEC_ROW(41), VEC_ROW(61)};
+static const launch_fn kLaunch[kNumK][3][2][kNumModes] = {
+    VEC_ROW(11), VEC_ROW(21), VEC_ROW(31), VEC_ROW(35), VEC_ROW(41), VEC_ROW(61)};
 // kLaunchBatch / kResidentBatch[K index][p - 1][space-time]: batched sums
 #define VEC_BPC(K, PC, F) {F<K, PC, 1, kModeSums, true>, F<K, PC, 2, kModeSums, true>}
 #define VEC_BROW(K, F) {VEC_BPC(K, 1, F), VEC_BPC(K, 2, F), VEC_BPC(K, 3, F)}
@@ -1289,12 +1292,12 @@ int vec_batch_make_plan(const vec_batch* bt, const vec_dataset* sets, const vec_
   for (int32_t b = 0; b < ns; ++b) {
     const vec_dataset& s = sets[b];
     if (s.reserved != 0 || s.n < 1 || s.n >= (int64_t)INT32_MAX) return VEC_EINVAL;
-    if (s.m < 0 || s.m > kKs[kNumBatchK - 1] - 1 || nu_code(s.smoothness) < 0) return VEC_EINVAL;
+    if (s.m < 0 || s.m > kBatchKs[kNumBatchK - 1] - 1 || nu_code(s.smoothness) < 0) return VEC_EINVAL;
     if (s.obs_offset < 0 || s.obs_offset > bt->n_total - s.n) return VEC_EINVAL;
     const int64_t nn_entries = s.n * (int64_t)(s.m + 1);
     if (s.nn_offset < 0 || s.nn_offset > bt->nn_total - nn_entries) return VEC_EINVAL;
     int c = 0;
-    while (s.m + 1 > kKs[c]) ++c;
+    while (s.m + 1 > kBatchKs[c]) ++c;
     cls[b] = c;
   }
   std::vector<int64_t> hsets((size_t)ns * kSetFields);

@@ -1412,10 +1412,18 @@ using resident_fn = int (*)();
   X(K, PC, 2, 2, false);             \
   X(K, PC, 2, 3, false)
 
-// Instantiated K values (K >= m + 1 is padded with identity rows); the
-// batched launches use the first kNumBatchK of them.
-constexpr int kNumK = 5;
-constexpr int kKs[kNumK] = {11, 21, 31, 41, 61};
+// single-problem modes of one range layout
+#define VECCHIA_FOR_NG_SINGLE(X, K, PC, NG) \
+  X(K, PC, NG, 0, false);                   \
+  X(K, PC, NG, 1, false);                   \
+  X(K, PC, NG, 2, false);                   \
+  X(K, PC, NG, 3, false)
+
+// Instantiated K values of the single-problem kernel (K >= m + 1 is padded
+// with rows that decouple) and the sizes of the batched classes.
+constexpr int kNumK = 6;
+constexpr int kKs[kNumK] = {11, 21, 31, 35, 41, 61};
 constexpr int kNumBatchK = 4;
+constexpr int kBatchKs[kNumBatchK] = {11, 21, 31, 41};
 
 }  // namespace vecchia

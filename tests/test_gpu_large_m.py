@@ -1,6 +1,7 @@
-"""Neighbourhoods of 42 to 61 observations (41 <= m <= 60, the paper's m = 60
-setting of its size study and its 60-neighbour kriging) on the fused kernel,
-in every single-problem mode, against the CPU oracle.
+"""Neighbourhoods of 32 to 61 observations on the fused kernel's larger sizes
+(K = 35 for 31 <= m <= 34, K = 41, K = 61 for 41 <= m <= 60: the paper's
+m = 60 setting of its size study and its 60-neighbour kriging), in every
+single-problem mode, against the CPU oracle.
 
 Tolerances as for the smaller sizes:
   loglik   |d| <= 1e-10 |loglik|
@@ -60,8 +61,9 @@ def _check(got, ref, tag):
                   <= 1e-8 * np.maximum(np.abs(ref["info"]), np.outer(sd, sd))), tag
 
 
-CASES = [(41, V.FAMILY_ISO, 0.5, 1), (45, V.FAMILY_ISO, 1.5, 3), (52, V.FAMILY_SPACETIME, 2.5, 2),
-         (60, V.FAMILY_ISO, 1.5, 1), (60, V.FAMILY_SPACETIME, 0.5, 3)]
+CASES = [(31, V.FAMILY_ISO, 0.5, 2), (34, V.FAMILY_SPACETIME, 1.5, 1), (41, V.FAMILY_ISO, 0.5, 1),
+         (45, V.FAMILY_ISO, 1.5, 3), (52, V.FAMILY_SPACETIME, 2.5, 2), (60, V.FAMILY_ISO, 1.5, 1),
+         (60, V.FAMILY_SPACETIME, 0.5, 3)]
 
 
 @pytest.mark.parametrize("m,family,nu,p", CASES)
@@ -99,7 +101,7 @@ def test_loglik_and_adjoint_match_oracle(m, family, nu, p):
             (m, beta, g, at["grad"])
 
 
-@pytest.mark.parametrize("m,nu", [(45, 2.5), (60, 0.5)])
+@pytest.mark.parametrize("m,nu", [(33, 1.5), (45, 2.5), (60, 0.5)])
 def test_kriging_weights_match_oracle(m, nu):
     w = _problem(500, m, V.FAMILY_ISO, nu, 2, seed=700 + m)
     ev = _ev(w)
@@ -131,7 +133,7 @@ def test_kriging_predict_with_60_neighbours():
 
 
 def test_ragged_tiles_and_tiny_problems():
-    for n, m in [(1, 60), (2, 60), (61, 60), (62, 60), (1029, 60), (3, 45)]:
+    for n, m in [(1, 60), (2, 60), (61, 60), (62, 60), (1029, 60), (3, 45), (35, 34), (36, 32)]:
         w = _problem(n, m, V.FAMILY_ISO, 0.5, 1, seed=n + m)
         _say(f"tiny/ragged n={n} m={m}")
         raw, ref = _oracle(w)
