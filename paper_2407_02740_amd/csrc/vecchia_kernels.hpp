@@ -318,10 +318,10 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // rows 0..K-1 packed at r(r-1)/2 (stores of a row run past its diagonal
   // into later rows, see the store below), then a sink for rows >= K
   constexpr int LPS = LPN + 1 + K;
-  // Above K = 31 a copy of Lt would take the LDS of another workgroup per
-  // CU (or leave no room for the pair factors): the back substitutions then
-  // run row by row on the factor in registers, one 16-lane sum per row.
-  constexpr bool kRowBack = K > 31;
+  // Above K = 21 the back substitutions run row by row on the factor in
+  // registers, one 16-lane sum per row, instead of on a copy of Lt in LDS
+  // (measured as fast at K = 31, and its LDS holds the pair factors).
+  constexpr bool kRowBack = K > 21;
   __shared__ double Lp[kGroupsPerBlock][(kLik || kRowBack) ? 1 : LPS];
   __shared__ double acc[kGroupsPerBlock][NRAW];
   // running product of conditional variances (mantissa, exponent)
@@ -332,7 +332,14 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
   // KP entries for the rows >= K and for the upper-triangle steps of an
   // unpaired last slot
   constexpr int NQ = K * (K + 1) / 2;
-  __shared__ double sfv[kGroupsPerBlock][kStoreF ? NQ + KP : 2];
+  // Space-time up to K = 31: two finished factors per pair instead,
+  // sigma2 (-f'(h)/h) times the squared spatial and time differences (the
+  // range derivatives up to 1/rho), interleaved at 2 (r(r+1)/2 + c); the
+  // sink is the single pair at NQ, every index clamped to it where it could
+  // pass it.  (At K = 31 with three covariates the larger sums would take
+  // the workgroup past a quarter of the CU's LDS: one factor there.)
+  constexpr bool kTwoF = kStoreF && NG == 2 && (K <= 21 || (K <= 31 && PC <= 2));
+  __shared__ double sfv[kGroupsPerBlock][kStoreF ? (kTwoF ? 2 * (NQ + 1) : NQ + KP) : 2];
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
@@ -599,12 +606,28 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
                           double& v1) {
       constexpr bool kExpo = decltype(expo_)::value;
       double h20 = kH2Floor, h21 = kH2Floor;
+      double hs0 = 0.0, hs1 = 0.0, ht0 = 0.0, ht1 = 0.0;  // kTwoF: space and time parts
+      if constexpr (kTwoF) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double t0 = za0[k] - zb0[k];
-        const double t1 = za1[k] - zb1[k];
-        h20 = __builtin_fma(t0, t0, h20);
-        h21 = __builtin_fma(t1, t1, h21);
+        for (int k = 0; k < 3; ++k) {
+          const double t0 = za0[k] - zb0[k];
+          const double t1 = za1[k] - zb1[k];
+          hs0 = __builtin_fma(t0, t0, hs0);
+          hs1 = __builtin_fma(t1, t1, hs1);
+        }
+        const double u0 = za0[3] - zb0[3], u1 = za1[3] - zb1[3];
+        ht0 = u0 * u0;
+        ht1 = u1 * u1;
+        h20 = (hs0 + kH2Floor) + ht0;
+        h21 = (hs1 + kH2Floor) + ht1;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double t0 = za0[k] - zb0[k];
+          const double t1 = za1[k] - zb1[k];
+          h20 = __builtin_fma(t0, t0, h20);
+          h21 = __builtin_fma(t1, t1, h21);
+        }
       }
       double hh0, hi0, hh1, hi1;
       dist_from_sq(h20, hh0, hi0);
@@ -631,7 +654,13 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
                                : sE0 * __builtin_fma(cf.a1, hh0, __builtin_fma(cf.a2, hi0, cf.a0));
       const double sF1 = kExpo ? sE1 * hi1
                                : sE1 * __builtin_fma(cf.a1, hh1, __builtin_fma(cf.a2, hi1, cf.a0));
-      if constexpr (kStoreF) {
+      if constexpr (kTwoF) {
+        const int j0 = idx0 < NQ ? idx0 : NQ, j1 = idx1 < NQ ? idx1 : NQ;
+        sfv[grp][2 * j0] = sF0 * hs0;
+        sfv[grp][2 * j0 + 1] = sF0 * ht0;
+        sfv[grp][2 * j1] = sF1 * hs1;
+        sfv[grp][2 * j1 + 1] = sF1 * ht1;
+      } else if constexpr (kStoreF) {
         // isotropic: the finished dSigma/drho entry, sF h^2 / rho (h^2 without
         // the floor, so that it is exactly 0 on the diagonal and at
         // coincident locations)
@@ -1017,18 +1046,18 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       constexpr int s = s_.value;
       const int a = row_of(s, l);
       base_a[s] = qrow_base[s];
-      if constexpr (NG == 2 || kRecomp) {
+      if constexpr ((NG == 2 && !kTwoF) || kRecomp) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) zrow[s][k] = rec[grp][rrow[s]][RZ + k];
       }
 #pragma unroll
       for (int g = 0; g < NG; ++g) gr[g][s] = 0.0;
     });
-    auto col_load = [&](auto b_, double& ub, double(&zb)[4], double(&Sv)[NS]) {
+    auto col_load = [&](auto b_, double& ub, double(&zb)[4], double(&Sv)[NS], double(&Tv)[NS]) {
       constexpr int b = decltype(b_)::value;
       constexpr int CB = b * (b + 1) / 2;
       ub = rec[grp][b][RU];
-      if constexpr (NG == 2 || kRecomp) {
+      if constexpr ((NG == 2 && !kTwoF) || kRecomp) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) zb[k] = rec[grp][b][RZ + k];
       }
@@ -1042,7 +1071,14 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
           idx = a + CB;
         else
           idx = (b <= a) ? base_a[s] + b : a + CB;
-        Sv[s] = sfv[grp][idx];
+        if constexpr (kTwoF) {
+          // only the last slot holds rows >= K, whose indices pass the sink
+          if constexpr (s == NS - 1 && K < 16 * NS) idx = idx < NQ ? idx : NQ;
+          Sv[s] = sfv[grp][2 * idx];
+          Tv[s] = sfv[grp][2 * idx + 1];
+        } else {
+          Sv[s] = sfv[grp][idx];
+        }
       });
     };
     // pair factor of (row of slot s, column b) again, as in phase 1 (the
@@ -1075,10 +1111,14 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
       });
     };
     // g_rho[row] += dSigma/drho (row, b) u_b for this lane's rows
-    auto accumulate_col = [&](double ub, const double(&zb)[4], const double(&Sv)[NS]) {
+    auto accumulate_col = [&](double ub, const double(&zb)[4], const double(&Sv)[NS],
+                              const double(&Tv)[NS]) {
       sfor<0, NS>([&](auto s_) {
         constexpr int s = s_.value;
-        if constexpr (NG == 1) {
+        if constexpr (kTwoF) {
+          gr[0][s] = __builtin_fma(Sv[s], ub, gr[0][s]);
+          gr[1][s] = __builtin_fma(Tv[s], ub, gr[1][s]);
+        } else if constexpr (NG == 1) {
           // stored directly as dSigma/drho for the isotropic family
           gr[0][s] = __builtin_fma(Sv[s], ub, gr[0][s]);
         } else {
@@ -1116,9 +1156,9 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         ubn = rec[grp][bn][RU];
 #pragma unroll
         for (int k = 0; k < 4; ++k) zbn[k] = rec[grp][bn][RZ + k];
-        double Sv[NS];
+        double Sv[NS], Tv[NS];
         recompute(zb, Sv);
-        accumulate_col(ub, zb, Sv);
+        accumulate_col(ub, zb, Sv, Tv);
       }
     } else {
       double alq[PF][NS];
@@ -1126,8 +1166,8 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
         sfor<0, NS>([&](auto s_) { al[s_.value] = rhs[0][s_.value] * idg[s_.value]; });
         back_prefetch(alq);
       }
-      double ubn, zbn[4], Svn[NS];
-      col_load(std::integral_constant<int, 0>{}, ubn, zbn, Svn);
+      double ubn, zbn[4], Svn[NS], Tvn[NS];
+      col_load(std::integral_constant<int, 0>{}, ubn, zbn, Svn, Tvn);
       sfor<0, K>([&](auto b_) {
         constexpr int b = b_.value;
         if constexpr (kAdj) {
@@ -1136,13 +1176,17 @@ __global__ __launch_bounds__(kThreads) void sums_kernel(const SumsArgs a) {
           else
             back_step(b_, alq, al);
         }
-        double ub = ubn, zb[4], Sv[NS];
+        double ub = ubn, zb[4], Sv[NS], Tv[NS];
 #pragma unroll
         for (int k = 0; k < 4; ++k) zb[k] = zbn[k];
-        sfor<0, NS>([&](auto s_) { Sv[s_.value] = Svn[s_.value]; });
-        if constexpr (b + 1 < K) col_load(std::integral_constant<int, b + 1>{}, ubn, zbn, Svn);
+        sfor<0, NS>([&](auto s_) {
+          Sv[s_.value] = Svn[s_.value];
+          Tv[s_.value] = Tvn[s_.value];
+        });
+        if constexpr (b + 1 < K)
+          col_load(std::integral_constant<int, b + 1>{}, ubn, zbn, Svn, Tvn);
         if constexpr (kRecomp) recompute(zb, Sv);
-        accumulate_col(ub, zb, Sv);
+        accumulate_col(ub, zb, Sv, Tv);
       });
     }
     if constexpr (NG == 2) {
